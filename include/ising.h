@@ -1,0 +1,167 @@
+/*
+ * ising.h -- C ABI of the MI355X Ising max-cut annealer.
+ *
+ * The method is the annealed local spin update of Cook, Zhao, Sato,
+ * Hiromoto and Tan, "GPU Ising Computing for Combinatorial Optimization
+ * Problems in VLSI Physical Design" (arXiv:1807.10750):
+ *   - a spin's local field is the weighted sum of its neighbours' spins and
+ *     the spin takes the value that minimises its local energy
+ *     (Sec. II-A, Eq. 1-2);
+ *   - every spin then flips with a global probability F_p that is lowered
+ *     sweep by sweep (Sec. IV-B, Algorithm 2);
+ *   - the max-cut value of Sec. III, Eq. (4) is read back from the spins.
+ *
+ * Conventions used throughout:
+ *   - Graph: symmetric CSR.  row_ptr is int64 [n+1] with row_ptr[0] = 0 and
+ *     row_ptr[n] = nnz; col is int32 [nnz]; w is int8 [nnz].  Every
+ *     undirected edge {u,v} appears as (u -> v, w) and (v -> u, w) with the
+ *     same weight.  Self-loops and repeated neighbours are rejected.  Rows
+ *     need not be sorted.  Vertex ids are the caller's; any internal
+ *     renumbering is invisible at this boundary.
+ *   - Max-cut mapping (Sec. III, Eq. 4-5): spin s_v = +1 / -1 is the side of
+ *     the cut.  The field is h_v = sum_u w_vu s_u and the update sets
+ *     s_v = -1 if h_v > 0, +1 if h_v < 0 and keeps s_v if h_v = 0; this is
+ *     the energy minimisation of Eq. (2) with J = -w, the sign that makes
+ *     the Ising ground state a maximum cut.
+ *   - energy  E   = sum over undirected edges of w_uv s_u s_v,
+ *     cut     cut = sum over undirected edges with s_u != s_v of w_uv,
+ *     so that 2 cut = W - E with W = sum of w over undirected edges.
+ *   - Random flips: spin v of replica r in sweep t flips after its update
+ *     iff x < T[t], x = word 0 of Philox4x32-10 with counter {v, t, r, 0}
+ *     and key {low32(seed), high32(seed)}; T[t] is the flip probability
+ *     F_p scaled to 2^32 (ISING_SCHED_*).  Random initial spins use counter
+ *     {v, 0, r, 1}: s = +1 iff bit 31 of word 0 is set.
+ *   - Replicas: a handle anneals R independent copies of the spins of one
+ *     graph; spin arrays are int8 [R][n], replica-major, values +1 / -1.
+ *   - Pointers: every graph or spin pointer may be host or device memory;
+ *     the library tells them apart.  Outputs documented as "host" must be
+ *     host memory.
+ *   - Streams: each call is ordered on the caller's stream (a hipStream_t
+ *     passed as void*; NULL is the default stream).  Calls that return
+ *     values into host memory synchronise that stream before returning.
+ *   - Ownership: isingCreate copies its inputs; the caller may free them on
+ *     return.  The handle owns every device buffer; isingDestroy frees them.
+ *   - Errors: no function aborts, throws or exits.  Each returns an
+ *     ising_status_t; on failure isingLastError() describes the cause.
+ *   - Threads: one handle must not be used from two threads at once;
+ *     distinct handles are independent.
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ising_graph_s *ising_graph_t;
+
+typedef enum {
+  ISING_OK = 0,
+  ISING_ERR_INVALID_ARGUMENT = 1, /* bad pointer, size, mode, range or spin value */
+  ISING_ERR_INVALID_GRAPH = 2,    /* row_ptr not 0..nnz monotone, or col out of range */
+  ISING_ERR_SELF_LOOP = 3,        /* an entry v -> v */
+  ISING_ERR_DUPLICATE_EDGE = 4,   /* a neighbour listed twice in one row */
+  ISING_ERR_ASYMMETRIC = 5,       /* (u -> v, w) without (v -> u, w) */
+  ISING_ERR_OVERFLOW = 6,         /* some row has sum |w| > INT32_MAX */
+  ISING_ERR_OUT_OF_MEMORY = 7,    /* host or device allocation failed */
+  ISING_ERR_DEVICE = 8            /* a HIP call or a kernel reported an error */
+} ising_status_t;
+
+/* Update order inside a sweep.
+ * DETERMINISTIC: vertices are updated colour class by colour class of a
+ *   greedy colouring (ising_coloring_t); the result equals a sequential
+ *   sweep that visits vertices in (colour, id) order, bit for bit.  This
+ *   generalises the checkerboard update the paper cites (Sec. IV-B).
+ * ASYNC: the paper's race-tolerant update (Sec. IV-B): within a sweep no
+ *   spin waits for another; a neighbour's value may be from this sweep or
+ *   the previous one.  Work is still issued colour class by colour class,
+ *   so most reads see this sweep's values.  Results vary from run to run;
+ *   they are judged by cut statistics. */
+typedef enum { ISING_MODE_DETERMINISTIC = 0, ISING_MODE_ASYNC = 1 } ising_mode_t;
+
+/* Greedy colouring rule.  FIRST_FIT visits vertices in increasing id;
+ * LARGEST_FIRST visits them by decreasing degree, then increasing id.  Each
+ * visited vertex takes the smallest colour no coloured neighbour has. */
+typedef enum { ISING_COLOR_FIRST_FIT = 0, ISING_COLOR_LARGEST_FIRST = 1 } ising_coloring_t;
+
+/* Flip-probability schedule F_p (Sec. IV-B, Algorithm 2: F_p is lowered
+ * after every sweep).  A probability p in [0,1] becomes the threshold
+ * T = min(2^32 - 1, floor(p * 2^32)).
+ * LINEAR: T[t] = Ts - floor((Ts - Te) * t / (M - 1)) for Ts >= Te (and the
+ *   mirror image for Ts < Te), t in [0, M), Ts, Te from p_start, p_end;
+ *   M = 1 gives Ts.
+ * EXPLICIT: T[t] = thresholds[t], a host array of n_sweeps entries. */
+typedef enum { ISING_SCHED_LINEAR = 0, ISING_SCHED_EXPLICIT = 1 } ising_sched_kind_t;
+
+typedef struct {
+  ising_sched_kind_t kind;
+  double p_start;               /* LINEAR only, in [0, 1] */
+  double p_end;                 /* LINEAR only, in [0, 1] */
+  int64_t n_sweeps;             /* M >= 1 */
+  const uint32_t *thresholds;   /* EXPLICIT only: host, n_sweeps entries */
+} ising_schedule_t;
+
+/* Build a handle for one graph and n_replicas spin copies (Sec. II-A: a
+ * general weighted graph of any topology).  Validates the graph in this
+ * order, reporting the first failure: arguments, structure, self-loop,
+ * duplicate, symmetry, overflow.  Then colours it, lays it out in device
+ * memory and allocates spins (all +1 until set or randomised).
+ * n >= 0, nnz >= 0, n < 2^31 - 64; n_replicas >= 1.  row_ptr/col/w may be
+ * host or device pointers (col and w may be NULL when nnz = 0).
+ * On success *out is a new handle; on failure *out is NULL. */
+ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                           const int32_t *col, const int8_t *w, ising_coloring_t coloring,
+                           int32_t n_replicas, void *stream);
+
+/* Set every replica's spins to random +-1 drawn from Philox counter domain 1
+ * (see the conventions above).  Stream-ordered, no synchronisation. */
+ising_status_t isingRandomizeSpins(ising_graph_t g, uint64_t seed, void *stream);
+
+/* Copy caller spins in: int8 [R][n], caller ids, every value +1 or -1
+ * (anything else: ISING_ERR_INVALID_ARGUMENT and the spins are unchanged).
+ * Host or device pointer; a device pointer is read on the stream and the
+ * call synchronises it to check the values. */
+ising_status_t isingSetSpins(ising_graph_t g, const int8_t *spins, void *stream);
+
+/* Run sweeps t = sweep_begin .. sweep_end-1 of the schedule (Algorithm 2):
+ * in each sweep every spin takes its local update and then flips iff its
+ * Philox draw is below T[t].  Chunked calls compose: [0,k) then [k,M) gives
+ * the same result as [0,M) in DETERMINISTIC mode.  Requires
+ * 0 <= sweep_begin <= sweep_end <= n_sweeps.  Stream-ordered; the schedule
+ * is copied before return.  Device faults surface at the next call that
+ * synchronises (isingCut, isingGetSpins). */
+ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *schedule, uint64_t seed,
+                           ising_mode_t mode, int64_t sweep_begin, int64_t sweep_end,
+                           void *stream);
+
+/* Cut value (Eq. 4) and energy (Eq. 5 with J = -w) of every replica:
+ * cut int64 [R], energy int64 [R] or NULL.  Host or device outputs; host
+ * outputs synchronise the stream.  Also checks 2 cut = W - E on the host
+ * when the outputs are host memory. */
+ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *stream);
+
+/* Copy spins out: int8 [R][n] in caller ids, host or device pointer.  A
+ * host destination synchronises the stream. */
+ising_status_t isingGetSpins(ising_graph_t g, int8_t *spins, void *stream);
+
+/* Colouring used by DETERMINISTIC mode: color int32 [n] (host), colour of
+ * every caller vertex; *n_colors its number of classes. */
+ising_status_t isingGetColoring(ising_graph_t g, int32_t *color, int32_t *n_colors);
+
+/* Sum of w over undirected edges (W in 2 cut = W - E). */
+ising_status_t isingTotalWeight(ising_graph_t g, int64_t *W);
+
+/* Free the handle and its device memory.  NULL is accepted. */
+ising_status_t isingDestroy(ising_graph_t g);
+
+/* Message for the last failed call on this thread ("" if none).  Valid
+ * until the next call on this thread. */
+const char *isingLastError(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISING_H */

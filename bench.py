@@ -1,0 +1,209 @@
+"""Benchmark of the Ising max-cut anneal on one MI355X.
+
+A step is one pass of the whole hot path over one synthetic graph that is
+already resident in HBM: random initial spins, the full annealing schedule
+(every sweep: local updates + annealed flips), and the cut/energy reduction.
+Graph ingest, validation and colouring happen once before timing (they are
+create-time host work, reported separately).
+
+Default workload: the 1,000,000-vertex power-law graph (exponent 2.5, mean
+degree 8, max degree 2000, weights +-1), 2000 sweeps of the linear flip
+schedule 0.1 -> 0, async mode -- the configuration whose edge stream is set
+against the HBM roofline.
+
+Prints one JSON line (see the repository's design notes for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+WORKLOADS = {
+    "powerlaw1m": dict(desc="power-law Chung-Lu n=1e6 alpha=2.5 mean-deg 8 max-deg 2000, w +-1, 2000 sweeps",
+                       sweeps=2000, replicas=1),
+    "torus200": dict(desc="2D torus 200x200 (n=40000, degree 4), w +-1, 5000 sweeps, 16 seeds as replicas",
+                     sweeps=5000, replicas=16),
+    "er800": dict(desc="Erdos-Renyi n=800 p=0.06, w +1, 1000 sweeps, 16 seeds as replicas",
+                  sweeps=1000, replicas=16),
+}
+
+
+def make_graph(name):
+    from paper_1807_10750_amd import graphs as G
+    if name == "powerlaw1m":
+        return G.powerlaw_chung_lu(1_000_000, alpha=2.5, mean_deg=8.0, max_deg=2000, weights="pm1", seed=1)
+    if name == "torus200":
+        return G.torus(200, 200, weights="pm1", seed=1)
+    if name == "er800":
+        return G.erdos_renyi(800, 0.06, "one", 1)
+    raise ValueError(name)
+
+
+def algorithmic_bytes_per_sweep(g, info):
+    """Bytes one sweep of one replica group must move in this layout.
+
+    Per directed edge: the 4-byte entry (neighbour slot, and the weight's sign
+    when every weight is +-1) plus 1 byte of weight otherwise.  Per vertex:
+    its 4-byte caller id (the flip counter) and the write of its new spin
+    mask (L bits).  Padding and work-item metadata are overhead, not counted.
+    """
+    per_edge = 4 if info["pm1"] else 5
+    L = info["replicas_per_group"]
+    return g.nnz * per_edge + g.n * 4 + g.n * L / 8.0
+
+
+def moved_bytes_per_sweep(info):
+    """Bytes the kernel streams per sweep per group, padding and metadata included."""
+    return info["edge_bytes"] + info["vertex_bytes"] + info["spin_bytes"] + 16 * info["items"]
+
+
+def cpu_baseline(g, sweeps_total, replicas, seed, budget_s):
+    """Time the CPU oracle (single-threaded C) on a bounded prefix of the schedule."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle as O
+    col, nc = O.color(g)
+    order = O.order(col, nc)
+    T = O.thresholds(0.1, 0.0, sweeps_total)
+    s0 = O.init_spins(g.n, 1, seed)
+    t0 = time.perf_counter()
+    O.anneal(g, order, s0, T, seed, 0, 1)
+    one = max(time.perf_counter() - t0, 1e-6)
+    sweeps = int(max(1, min(sweeps_total, budget_s / one)))
+    t0 = time.perf_counter()
+    O.anneal(g, order, s0, T, seed, 0, sweeps)
+    dt = time.perf_counter() - t0
+    return {"value": g.n * sweeps / dt, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sweeps} of {sweeps_total} sweeps, 1 replica, same graph, sequential "
+                      f"(colour, id) order, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="powerlaw1m", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="async", choices=["async", "det"])
+    ap.add_argument("--coloring", default="ff", choices=["ff", "lf"])
+    ap.add_argument("--sweeps", type=int, default=None, help="override the schedule length")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
+    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per anneal launch")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1807_10750_amd import ising as I
+
+    wl = WORKLOADS[args.workload]
+    M = args.sweeps or wl["sweeps"]
+    R = wl["replicas"]
+    mode = I.MODE_ASYNC if args.mode == "async" else I.MODE_DETERMINISTIC
+    torch.cuda.set_device(0)
+
+    t0 = time.perf_counter()
+    g = make_graph(args.workload)
+    gen_s = time.perf_counter() - t0
+    print(f"# graph {args.workload}: n={g.n} m={g.m} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    cl = torch.from_numpy(g.col).to(dev)
+    ww = torch.from_numpy(g.w).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gr = I.Graph(rp, cl, ww, n=g.n, replicas=R,
+                 coloring=I.COLOR_LARGEST_FIRST if args.coloring == "lf" else I.COLOR_FIRST_FIT)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    del rp, cl, ww
+    info = gr.info()
+    print(f"# create {create_s:.2f}s info={info}", file=sys.stderr, flush=True)
+    sch = I.make_schedule(0.1, 0.0, M)
+    cut = torch.zeros(R, dtype=torch.int64, device=dev)
+    energy = torch.zeros(R, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        gr.randomize(1000 + i)
+        gr.anneal(sch, 1000 + i, mode)
+        gr.cut_device(cut, energy)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    print("# warmup done", file=sys.stderr, flush=True)
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for i in range(args.steps):
+        gr.randomize(2000 + i)
+        ev[i][0].record(stream)
+        gr.anneal(sch, 2000 + i, mode)
+        ev[i][1].record(stream)
+        gr.cut_device(cut, energy)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    anneal_ms = [a.elapsed_time(b) for a, b in ev]
+    cuts = cut.cpu().numpy()
+    ms_step = total_ms / args.steps
+    value = g.n * R * M * args.steps / (total_ms / 1e3)
+
+    alg = algorithmic_bytes_per_sweep(g, info) * info["n_groups"] * M
+    moved = moved_bytes_per_sweep(info) * info["n_groups"] * M
+    mean_anneal_s = float(np.mean(anneal_ms)) / 1e3
+    achieved = alg / mean_anneal_s / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        traffic = json.load(open(args.traffic)).get(args.workload)
+    out = {
+        "metric": "spin-updates/sec",
+        "value": value,
+        "unit": "spin-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "name": args.workload, "n": g.n, "nnz": g.nnz,
+                   "sweeps": M, "replicas": R, "mode": args.mode, "coloring": args.coloring,
+                   "colors": info["n_colors"], "grid": info["grid"], "block": info["block"],
+                   "lds_spins": bool(info["uses_lds"]), "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_anneal", "anneal_ms_mean": float(np.mean(anneal_ms)),
+                     "anneal_ms_min": float(np.min(anneal_ms)),
+                     "algorithmic_bytes_per_launch": alg, "moved_bytes_per_launch": moved},
+        "final_cut_last_step": int(cuts[0]),
+        "create_s": create_s,
+    }
+    if args.cpu_budget > 0:
+        print("# cpu baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(g, M, R, 1000, args.cpu_budget)
+        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+    gr.close()
+
+
+if __name__ == "__main__":
+    main()

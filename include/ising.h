@@ -153,6 +153,24 @@ ising_status_t isingGetColoring(ising_graph_t g, int32_t *color, int32_t *n_colo
 /* Sum of w over undirected edges (W in 2 cut = W - E). */
 ising_status_t isingTotalWeight(ising_graph_t g, int64_t *W);
 
+/* Layout and launch facts of a handle, for benchmarks and tests. */
+typedef struct {
+  int64_t n_slots;          /* vertices after padding each colour class to a multiple of 64 */
+  int32_t n_colors;         /* colour classes = phases of a deterministic sweep */
+  int32_t replicas_per_group; /* replicas annealed together from one read of the edges */
+  int32_t n_groups;         /* replica groups; the edge stream is read once per group per sweep */
+  int32_t uses_lds;         /* 1 if neighbour spins are gathered from an LDS copy */
+  int32_t grid;             /* workgroups of the anneal launch */
+  int32_t block;            /* threads per workgroup */
+  int32_t pm1;              /* 1 if every weight is +-1 (sign packed into the edge entry) */
+  int64_t edge_bytes;       /* bytes of the edge stream read once per sweep per group */
+  int64_t vertex_bytes;     /* bytes of per-vertex data read once per sweep per group */
+  int64_t spin_bytes;       /* bytes of one group's packed spin state */
+  int64_t items;            /* wavefront work items per sweep */
+} ising_info_t;
+
+ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info);
+
 /* Free the handle and its device memory.  NULL is accepted. */
 ising_status_t isingDestroy(ising_graph_t g);
 

@@ -1,0 +1,565 @@
+// api.cpp -- the C ABI declared in include/ising.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ising.h"
+#include "kernels.h"
+#include "prep.h"
+
+using namespace ising;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ising_status_t fail(ising_status_t st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+ising_status_t hip_fail(hipError_t e, const char *what) {
+  return fail(e == hipErrorOutOfMemory ? ISING_ERR_OUT_OF_MEMORY : ISING_ERR_DEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                   \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr size_t kLdsBudget = 160 * 1024 - 2048;  // gfx950 LDS per workgroup, minus static use
+
+bool is_device_ptr(const void *p) {
+  if (p == nullptr) return false;
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+int64_t env_int(const char *name, int64_t dflt) {
+  const char *s = std::getenv(name);
+  if (s == nullptr || *s == 0) return dflt;
+  return std::strtoll(s, nullptr, 10);
+}
+
+int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x && p < 32) p <<= 1;
+  return p;
+}
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev) (void)hipSetDevice(dev);
+    dev_ = dev;
+  }
+  ~DeviceGuard() {
+    if (prev_ >= 0 && prev_ != dev_) (void)hipSetDevice(prev_);
+  }
+
+ private:
+  int prev_ = -1, dev_ = 0;
+};
+
+}  // namespace
+
+struct ising_graph_s {
+  int device = 0;
+  int64_t n = 0, nnz = 0;
+  int32_t R = 1;
+  int32_t n_colors = 0;
+  std::vector<int32_t> color;
+  int64_t W = 0;
+  HostLayout lay;            // host copy (entries/wts released after upload)
+  int64_t entry_bytes = 0;   // edge stream bytes per sweep (entries + weights)
+  int L = 1, n_groups = 1;
+  uint32_t n_words = 0;      // spin words per group
+  bool use_lds = false;
+  size_t lds_bytes = 0;
+  int grid = 1, nw = 16;
+  // device buffers
+  void *d_entries = nullptr;
+  uint32_t *d_wts4 = nullptr;
+  int32_t *d_vid = nullptr;
+  Item *d_items = nullptr;
+  uint32_t *d_wave_ptr = nullptr;
+  uint32_t *d_cls_w64 = nullptr;
+  uint32_t *d_spins = nullptr;
+  uint32_t *d_thr = nullptr;
+  int64_t thr_cap = 0;
+  uint32_t *d_bar = nullptr;   // [0] barrier counter, [1] anneal error flag, [2] spin-check flag
+  unsigned long long *d_cut = nullptr;
+  int8_t *d_stage = nullptr;
+  // schedule cache
+  bool thr_valid = false;
+  double ps = -1, pe = -1;
+  int64_t M = 0;
+  uint32_t *h_thr = nullptr;   // pinned staging of the thresholds
+  int64_t h_thr_cap = 0;
+};
+
+namespace {
+
+template <typename T>
+ising_status_t dev_alloc(T **p, size_t bytes, const char *what) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(p), bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_fail(e, what);
+  }
+  return ISING_OK;
+}
+
+void free_all(ising_graph_s *g) {
+  void *bufs[] = {g->d_entries, g->d_wts4, g->d_vid, g->d_items, g->d_wave_ptr, g->d_cls_w64,
+                  g->d_spins, g->d_thr, g->d_bar, g->d_cut, g->d_stage};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  if (g->h_thr) (void)hipHostFree(g->h_thr);
+}
+
+// Copies an array given by a host or device pointer into a host vector.
+template <typename T>
+ising_status_t fetch(std::vector<T> *dst, const T *src, int64_t count, const char *what) {
+  try {
+    dst->resize((size_t)count);
+  } catch (const std::bad_alloc &) {
+    return fail(ISING_ERR_OUT_OF_MEMORY, std::string("host allocation failed for ") + what);
+  }
+  if (count == 0) return ISING_OK;
+  if (is_device_ptr(src)) {
+    HIP_TRY(hipMemcpy(dst->data(), src, sizeof(T) * (size_t)count, hipMemcpyDeviceToHost), what);
+  } else {
+    std::memcpy(dst->data(), src, sizeof(T) * (size_t)count);
+  }
+  return ISING_OK;
+}
+
+ising_status_t upload(void *dst, const void *src, size_t bytes, const char *what) {
+  if (bytes == 0) return ISING_OK;
+  HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), what);
+  return ISING_OK;
+}
+
+// Thresholds T[t] of a linear schedule (see ising.h).
+uint32_t prob_threshold(double p) {
+  const double x = p * 4294967296.0;  // exact scaling by 2^32
+  return x >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)x;
+}
+
+void linear_thresholds(double ps, double pe, int64_t M, uint32_t *T) {
+  const uint32_t a = prob_threshold(ps), b = prob_threshold(pe);
+  const bool down = a >= b;
+  const uint64_t span = down ? (uint64_t)(a - b) : (uint64_t)(b - a);
+  for (int64_t t = 0; t < M; ++t) {
+    uint64_t step = 0;
+    if (M > 1) step = (uint64_t)(((unsigned __int128)span * (uint64_t)t) / (uint64_t)(M - 1));
+    T[t] = down ? a - (uint32_t)step : a + (uint32_t)step;
+  }
+}
+
+ising_status_t ensure_thresholds(ising_graph_s *g, const ising_schedule_t *s, hipStream_t st) {
+  const bool cached = s->kind == ISING_SCHED_LINEAR && g->thr_valid && g->ps == s->p_start &&
+                      g->pe == s->p_end && g->M == s->n_sweeps;
+  if (cached) return ISING_OK;
+  // previous anneals on this stream may still read the old table
+  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (s->n_sweeps > g->thr_cap) {
+    if (g->d_thr) (void)hipFree(g->d_thr);
+    g->d_thr = nullptr;
+    g->thr_cap = 0;
+    ising_status_t r = dev_alloc(&g->d_thr, sizeof(uint32_t) * (size_t)s->n_sweeps, "threshold table");
+    if (r != ISING_OK) return r;
+    g->thr_cap = s->n_sweeps;
+  }
+  if (s->n_sweeps > g->h_thr_cap) {
+    if (g->h_thr) (void)hipHostFree(g->h_thr);
+    g->h_thr = nullptr;
+    g->h_thr_cap = 0;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&g->h_thr), sizeof(uint32_t) * (size_t)s->n_sweeps),
+            "pinned threshold staging");
+    g->h_thr_cap = s->n_sweeps;
+  }
+  if (s->kind == ISING_SCHED_LINEAR)
+    linear_thresholds(s->p_start, s->p_end, s->n_sweeps, g->h_thr);
+  else
+    std::memcpy(g->h_thr, s->thresholds, sizeof(uint32_t) * (size_t)s->n_sweeps);
+  HIP_TRY(hipMemcpyAsync(g->d_thr, g->h_thr, sizeof(uint32_t) * (size_t)s->n_sweeps, hipMemcpyHostToDevice, st),
+          "threshold upload");
+  g->thr_valid = s->kind == ISING_SCHED_LINEAR;
+  g->ps = s->p_start;
+  g->pe = s->p_end;
+  g->M = s->n_sweeps;
+  return ISING_OK;
+}
+
+uint32_t group_r_count(const ising_graph_s *g, int grp) {
+  const int r0 = grp * g->L;
+  return (uint32_t)std::min(g->L, g->R - r0);
+}
+
+ising_status_t check_flags(ising_graph_s *g, hipStream_t st) {
+  uint32_t flags[3] = {0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(flags, g->d_bar, sizeof flags, hipMemcpyDeviceToHost, st), "flag readback");
+  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (flags[1] != 0) return fail(ISING_ERR_DEVICE, "an anneal grid barrier timed out");
+  return ISING_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *isingLastError(void) { return g_last_error.c_str(); }
+
+ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                           const int32_t *col, const int8_t *w, ising_coloring_t coloring,
+                           int32_t n_replicas, void *stream) {
+  g_last_error.clear();
+  if (out == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (n < 0 || nnz < 0 || n >= (int64_t)0x7FFFFFFF - 64)
+    return fail(ISING_ERR_INVALID_ARGUMENT, "n or nnz out of range");
+  if (row_ptr == nullptr || (nnz > 0 && (col == nullptr || w == nullptr)))
+    return fail(ISING_ERR_INVALID_ARGUMENT, "graph pointer is NULL");
+  if (n_replicas < 1) return fail(ISING_ERR_INVALID_ARGUMENT, "n_replicas < 1");
+  if (coloring != ISING_COLOR_FIRST_FIT && coloring != ISING_COLOR_LARGEST_FIRST)
+    return fail(ISING_ERR_INVALID_ARGUMENT, "unknown colouring");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (is_device_ptr(row_ptr) || is_device_ptr(col) || is_device_ptr(w)) {
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  }
+  std::vector<int64_t> rp;
+  std::vector<int32_t> cl;
+  std::vector<int8_t> wt;
+  ising_status_t r;
+  if ((r = fetch(&rp, row_ptr, n + 1, "row_ptr")) != ISING_OK) return r;
+  if ((r = fetch(&cl, col, nnz, "col")) != ISING_OK) return r;
+  if ((r = fetch(&wt, w, nnz, "w")) != ISING_OK) return r;
+  HostCSR csr;
+  csr.n = n;
+  csr.nnz = nnz;
+  csr.row_ptr = rp.data();
+  csr.col = cl.data();
+  csr.w = wt.data();
+
+  ising_graph_s *g = new (std::nothrow) ising_graph_s();
+  if (g == nullptr) return fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed");
+  auto bail = [&](ising_status_t s) {
+    free_all(g);
+    delete g;
+    return s;
+  };
+  g->n = n;
+  g->nnz = nnz;
+  g->R = n_replicas;
+  if (hipGetDevice(&g->device) != hipSuccess) return bail(fail(ISING_ERR_DEVICE, "no HIP device"));
+  std::string msg;
+  int v = validate_graph(csr, &g->W, &msg);
+  if (v != kPrepOk) return bail(fail((ising_status_t)v, msg));
+  try {
+    g->n_colors = greedy_coloring(csr, coloring == ISING_COLOR_LARGEST_FIRST, &g->color);
+  } catch (const std::bad_alloc &) {
+    return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed while colouring"));
+  }
+  const int64_t long_deg = std::max<int64_t>(4, env_int("ISING_LONG_DEG", 64));
+  v = build_layout(csr, g->color, g->n_colors, long_deg, &g->lay, &msg);
+  if (v != kPrepOk) return bail(fail((ising_status_t)v, msg));
+  if (!check_layout(g->lay, &msg)) return bail(fail(ISING_ERR_DEVICE, "internal layout check: " + msg));
+  HostLayout &lay = g->lay;
+
+  // replica packing: as many replicas per pass as fit an LDS copy of the state
+  int L = pow2_at_least(n_replicas);
+  const bool allow_lds = env_int("ISING_NO_LDS", 0) == 0;
+  auto state_bytes = [&](int l) { return (size_t)lay.n_slots * (size_t)l / 8; };
+  while (allow_lds && L > 1 && state_bytes(L) > kLdsBudget) L >>= 1;
+  g->use_lds = allow_lds && state_bytes(L) <= kLdsBudget;
+  if (!g->use_lds) L = pow2_at_least(n_replicas);
+  g->L = L;
+  g->n_groups = (n_replicas + L - 1) / L;
+  g->n_words = (uint32_t)((size_t)lay.n_slots * (size_t)L / 32);
+  g->lds_bytes = g->use_lds ? std::max<size_t>(state_bytes(L), 16) : 0;
+
+  // grid: enough workgroups for the largest colour class, at most what is co-resident
+  int per_cu = 0;
+  {
+    hipError_t e = anneal_occupancy(L, lay.pm1, g->use_lds, g->lds_bytes, &per_cu);
+    if (e != hipSuccess) return bail(hip_fail(e, "occupancy query"));
+  }
+  hipDeviceProp_t prop;
+  {
+    hipError_t e = hipGetDeviceProperties(&prop, g->device);
+    if (e != hipSuccess) return bail(hip_fail(e, "hipGetDeviceProperties"));
+  }
+  const int waves_per_block = kAnnealBlock / 64;
+  const int max_grid = std::max(1, per_cu) * prop.multiProcessorCount;
+  uint32_t max_phase = 0;
+  for (int32_t p = 0; p < lay.n_phases; ++p)
+    max_phase = std::max(max_phase, lay.phase_items[p + 1] - lay.phase_items[p]);
+  int grid = (int)std::min<int64_t>(max_grid, std::max<int64_t>(1, (max_phase + waves_per_block - 1) / waves_per_block));
+  const int64_t want = env_int("ISING_GRID", 0);
+  if (want > 0) grid = (int)std::min<int64_t>(want, max_grid);
+  g->grid = grid;
+  g->nw = grid * waves_per_block;
+  std::vector<uint32_t> wave_ptr = partition_waves(lay, g->nw);
+  std::vector<uint32_t> cls_w64(lay.n_phases + 1);
+  for (int32_t p = 0; p <= lay.n_phases; ++p) cls_w64[p] = (uint32_t)((uint64_t)lay.cls_begin[p] * L / 64);
+
+  // device buffers
+  const size_t entry_b = lay.entries.size() * sizeof(uint32_t);
+  g->entry_bytes = (int64_t)entry_b + (int64_t)lay.wts.size();
+  if ((r = dev_alloc(&g->d_entries, entry_b, "edge stream")) != ISING_OK) return bail(r);
+  if ((r = upload(g->d_entries, lay.entries.data(), entry_b, "edge stream upload")) != ISING_OK) return bail(r);
+  if (!lay.pm1) {
+    if ((r = dev_alloc(&g->d_wts4, lay.wts.size(), "weights")) != ISING_OK) return bail(r);
+    if ((r = upload(g->d_wts4, lay.wts.data(), lay.wts.size(), "weights upload")) != ISING_OK) return bail(r);
+  }
+  if ((r = dev_alloc(&g->d_vid, sizeof(int32_t) * lay.vid.size(), "slot table")) != ISING_OK) return bail(r);
+  if ((r = upload(g->d_vid, lay.vid.data(), sizeof(int32_t) * lay.vid.size(), "slot upload")) != ISING_OK) return bail(r);
+  if ((r = dev_alloc(&g->d_items, sizeof(Item) * lay.items.size(), "items")) != ISING_OK) return bail(r);
+  if ((r = upload(g->d_items, lay.items.data(), sizeof(Item) * lay.items.size(), "items upload")) != ISING_OK) return bail(r);
+  if ((r = dev_alloc(&g->d_wave_ptr, sizeof(uint32_t) * wave_ptr.size(), "wave table")) != ISING_OK) return bail(r);
+  if ((r = upload(g->d_wave_ptr, wave_ptr.data(), sizeof(uint32_t) * wave_ptr.size(), "wave upload")) != ISING_OK) return bail(r);
+  if ((r = dev_alloc(&g->d_cls_w64, sizeof(uint32_t) * cls_w64.size(), "class table")) != ISING_OK) return bail(r);
+  if ((r = upload(g->d_cls_w64, cls_w64.data(), sizeof(uint32_t) * cls_w64.size(), "class upload")) != ISING_OK) return bail(r);
+  if ((r = dev_alloc(&g->d_spins, sizeof(uint32_t) * (size_t)g->n_words * g->n_groups, "spins")) != ISING_OK) return bail(r);
+  if ((r = dev_alloc(&g->d_bar, sizeof(uint32_t) * 4, "flags")) != ISING_OK) return bail(r);
+  if ((r = dev_alloc(&g->d_cut, sizeof(unsigned long long) * 2 * (size_t)n_replicas + 16, "cut")) != ISING_OK) return bail(r);
+  if ((r = dev_alloc(&g->d_stage, (size_t)n * (size_t)n_replicas, "spin staging")) != ISING_OK) return bail(r);
+  {
+    hipError_t e = launch_fill_u32(g->d_spins, g->n_words * (uint32_t)g->n_groups, 0xFFFFFFFFu, st);
+    if (e == hipSuccess) e = launch_fill_u32(g->d_bar, 4, 0u, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(hip_fail(e, "initialising spins"));
+  }
+  // the edge stream is on the device now; keep only what later calls need
+  std::vector<uint32_t>().swap(lay.entries);
+  std::vector<int8_t>().swap(lay.wts);
+  *out = g;
+  return ISING_OK;
+}
+
+ising_status_t isingDestroy(ising_graph_t g) {
+  g_last_error.clear();
+  if (g == nullptr) return ISING_OK;
+  DeviceGuard guard(g->device);
+  free_all(g);
+  delete g;
+  return ISING_OK;
+}
+
+ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info) {
+  g_last_error.clear();
+  if (g == nullptr || info == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
+  info->n_slots = g->lay.n_slots;
+  info->n_colors = g->n_colors;
+  info->replicas_per_group = g->L;
+  info->n_groups = g->n_groups;
+  info->uses_lds = g->use_lds ? 1 : 0;
+  info->grid = g->grid;
+  info->block = kAnnealBlock;
+  info->pm1 = g->lay.pm1 ? 1 : 0;
+  info->edge_bytes = g->entry_bytes;
+  info->vertex_bytes = (int64_t)g->lay.n_slots * 4;
+  info->spin_bytes = (int64_t)g->n_words * 4;
+  info->items = (int64_t)g->lay.items.size();
+  return ISING_OK;
+}
+
+ising_status_t isingTotalWeight(ising_graph_t g, int64_t *W) {
+  g_last_error.clear();
+  if (g == nullptr || W == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
+  *W = g->W;
+  return ISING_OK;
+}
+
+ising_status_t isingGetColoring(ising_graph_t g, int32_t *color, int32_t *n_colors) {
+  g_last_error.clear();
+  if (g == nullptr || n_colors == nullptr || (color == nullptr && g->n > 0))
+    return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (g->n > 0) std::memcpy(color, g->color.data(), sizeof(int32_t) * (size_t)g->n);
+  *n_colors = g->n_colors;
+  return ISING_OK;
+}
+
+ising_status_t isingRandomizeSpins(ising_graph_t g, uint64_t seed, void *stream) {
+  g_last_error.clear();
+  if (g == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL handle");
+  DeviceGuard guard(g->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (int grp = 0; grp < g->n_groups; ++grp) {
+    HIP_TRY(launch_randomize(g->L, g->d_spins + (size_t)grp * g->n_words, g->d_vid, g->n_words,
+                             (uint32_t)(grp * g->L), group_r_count(g, grp), seed, st),
+            "randomize launch");
+  }
+  return ISING_OK;
+}
+
+ising_status_t isingSetSpins(ising_graph_t g, const int8_t *spins, void *stream) {
+  g_last_error.clear();
+  if (g == nullptr || (spins == nullptr && g->n > 0)) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (g->n == 0) return ISING_OK;
+  DeviceGuard guard(g->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t count = g->n * (int64_t)g->R;
+  const int8_t *src = spins;
+  if (is_device_ptr(spins)) {
+    HIP_TRY(launch_fill_u32(g->d_bar + 2, 1, 0u, st), "flag reset");
+    HIP_TRY(launch_check_spins(spins, count, g->d_bar + 2, st), "spin check launch");
+    uint32_t bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, g->d_bar + 2, sizeof bad, hipMemcpyDeviceToHost, st), "flag readback");
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (bad) return fail(ISING_ERR_INVALID_ARGUMENT, "spin values must be +1 or -1");
+  } else {
+    for (int64_t i = 0; i < count; ++i)
+      if (spins[i] != 1 && spins[i] != -1)
+        return fail(ISING_ERR_INVALID_ARGUMENT, "spin value at index " + std::to_string(i) + " is not +1 or -1");
+    HIP_TRY(hipMemcpyAsync(g->d_stage, spins, (size_t)count, hipMemcpyHostToDevice, st), "spin upload");
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    src = g->d_stage;
+  }
+  for (int grp = 0; grp < g->n_groups; ++grp)
+    HIP_TRY(launch_set_spins(g->L, g->d_spins + (size_t)grp * g->n_words, g->d_vid, g->n_words, src, g->n,
+                             (uint32_t)(grp * g->L), group_r_count(g, grp), st),
+            "set-spins launch");
+  return ISING_OK;
+}
+
+ising_status_t isingGetSpins(ising_graph_t g, int8_t *spins, void *stream) {
+  g_last_error.clear();
+  if (g == nullptr || (spins == nullptr && g->n > 0)) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (g->n == 0) return ISING_OK;
+  DeviceGuard guard(g->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool dev = is_device_ptr(spins);
+  int8_t *dst = dev ? spins : g->d_stage;
+  for (int grp = 0; grp < g->n_groups; ++grp)
+    HIP_TRY(launch_get_spins(g->L, g->d_spins + (size_t)grp * g->n_words, g->d_vid, (uint32_t)g->lay.n_slots,
+                             dst, g->n, (uint32_t)(grp * g->L), group_r_count(g, grp), st),
+            "get-spins launch");
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(spins, g->d_stage, (size_t)(g->n * g->R), hipMemcpyDeviceToHost, st), "spin readback");
+    return check_flags(g, st);
+  }
+  return ISING_OK;
+}
+
+ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *s, uint64_t seed, ising_mode_t mode,
+                           int64_t sweep_begin, int64_t sweep_end, void *stream) {
+  g_last_error.clear();
+  if (g == nullptr || s == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (mode != ISING_MODE_DETERMINISTIC && mode != ISING_MODE_ASYNC)
+    return fail(ISING_ERR_INVALID_ARGUMENT, "unknown mode");
+  if (s->n_sweeps < 1 || s->n_sweeps > ((int64_t)1 << 32))
+    return fail(ISING_ERR_INVALID_ARGUMENT, "n_sweeps must be in [1, 2^32]");
+  if (s->kind == ISING_SCHED_LINEAR) {
+    if (!(s->p_start >= 0.0 && s->p_start <= 1.0 && s->p_end >= 0.0 && s->p_end <= 1.0))
+      return fail(ISING_ERR_INVALID_ARGUMENT, "probabilities must lie in [0, 1]");
+  } else if (s->kind == ISING_SCHED_EXPLICIT) {
+    if (s->thresholds == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "thresholds is NULL");
+  } else {
+    return fail(ISING_ERR_INVALID_ARGUMENT, "unknown schedule kind");
+  }
+  if (sweep_begin < 0 || sweep_begin > sweep_end || sweep_end > s->n_sweeps)
+    return fail(ISING_ERR_INVALID_ARGUMENT, "need 0 <= sweep_begin <= sweep_end <= n_sweeps");
+  if (sweep_begin == sweep_end || g->n == 0) return ISING_OK;
+  DeviceGuard guard(g->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  ising_status_t r = ensure_thresholds(g, s, st);
+  if (r != ISING_OK) return r;
+
+  AnnealArgs a{};
+  a.entries = reinterpret_cast<const uint4 *>(g->d_entries);
+  a.wts4 = g->d_wts4;
+  a.vid = g->d_vid;
+  a.items = g->d_items;
+  a.wave_ptr = g->d_wave_ptr;
+  a.cls_w64 = g->d_cls_w64;
+  a.thr = g->d_thr;
+  a.bar = g->d_bar;
+  a.n_words = g->n_words;
+  a.n_phases = g->lay.n_phases;
+  a.nw = g->nw;
+  a.async_mode = mode == ISING_MODE_ASYNC ? 1 : 0;
+  a.seed_lo = (uint32_t)seed;
+  a.seed_hi = (uint32_t)(seed >> 32);
+  a.spin_limit = (uint32_t)std::max<int64_t>(1000, env_int("ISING_BARRIER_POLLS", 20000000));
+  // keep the barrier counter below 2^31 within one launch
+  const int64_t barriers_per_sweep = g->grid > 1 ? (a.async_mode ? 1 : std::max(1, g->lay.n_phases)) : 0;
+  int64_t chunk = sweep_end - sweep_begin;
+  if (barriers_per_sweep > 0) chunk = std::max<int64_t>(1, ((int64_t)1 << 30) / (barriers_per_sweep * g->grid));
+  for (int grp = 0; grp < g->n_groups; ++grp) {
+    a.spins = g->d_spins + (size_t)grp * g->n_words;
+    a.r0 = (uint32_t)(grp * g->L);
+    a.r_count = group_r_count(g, grp);
+    for (int64_t t0 = sweep_begin; t0 < sweep_end; t0 += chunk) {
+      a.t_begin = t0;
+      a.t_end = std::min(sweep_end, t0 + chunk);
+      HIP_TRY(launch_fill_u32(g->d_bar, 1, 0u, st), "barrier reset");
+      HIP_TRY(launch_anneal(g->L, g->lay.pm1, g->use_lds, a, g->grid, g->lds_bytes, st), "anneal launch");
+    }
+  }
+  return ISING_OK;
+}
+
+ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *stream) {
+  g_last_error.clear();
+  if (g == nullptr || cut == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
+  DeviceGuard guard(g->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool dev_cut = is_device_ptr(cut);
+  const bool dev_e = energy != nullptr && is_device_ptr(energy);
+  if (energy != nullptr && dev_cut != dev_e)
+    return fail(ISING_ERR_INVALID_ARGUMENT, "cut and energy must both be host or both be device memory");
+  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(g->d_cut), 4 * (uint32_t)g->R, 0u, st), "cut reset");
+  for (int grp = 0; grp < g->n_groups; ++grp)
+    for (uint32_t j = 0; j < group_r_count(g, grp); ++j) {
+      CutArgs c{};
+      c.entries = reinterpret_cast<const uint4 *>(g->d_entries);
+      c.wts4 = g->d_wts4;
+      c.vid = g->d_vid;
+      c.items = g->d_items;
+      c.n_items = (uint32_t)g->lay.items.size();
+      c.spins = g->d_spins + (size_t)grp * g->n_words;
+      c.out = g->d_cut + 2 * (size_t)(grp * g->L + j);
+      c.bit = j;
+      if (c.n_items > 0) HIP_TRY(launch_cut(g->L, g->lay.pm1, c, st), "cut launch");
+    }
+  if (dev_cut) {
+    HIP_TRY(launch_cut_finalize(g->d_cut, g->R, cut, energy, st), "cut finalize");
+    return ISING_OK;
+  }
+  std::vector<unsigned long long> sums(2 * (size_t)g->R);
+  HIP_TRY(hipMemcpyAsync(sums.data(), g->d_cut, sizeof(unsigned long long) * sums.size(), hipMemcpyDeviceToHost, st),
+          "cut readback");
+  {
+    ising_status_t r = check_flags(g, st);
+    if (r != ISING_OK) return r;
+  }
+  for (int32_t i = 0; i < g->R; ++i) {
+    const int64_t e_dir = (int64_t)sums[2 * i], c_dir = (int64_t)sums[2 * i + 1];
+    if ((e_dir & 1) || (c_dir & 1)) return fail(ISING_ERR_DEVICE, "cut sums over directed edges are odd");
+    const int64_t E = e_dir / 2, C = c_dir / 2;
+    if (2 * C != g->W - E) return fail(ISING_ERR_DEVICE, "cut/energy identity 2 cut = W - E failed");
+    cut[i] = C;
+    if (energy) energy[i] = E;
+  }
+  return ISING_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,290 @@
+// prep.cpp -- host preparation of a graph handle (see prep.h).
+#include "prep.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <limits>
+#include <new>
+
+namespace ising {
+
+namespace {
+
+std::string at(int64_t row, int64_t k) {
+  char buf[96];
+  if (k >= 0)
+    std::snprintf(buf, sizeof buf, "row %lld entry %lld", (long long)row, (long long)k);
+  else
+    std::snprintf(buf, sizeof buf, "row %lld", (long long)row);
+  return buf;
+}
+
+}  // namespace
+
+int validate_graph(const HostCSR &g, int64_t *W_out, std::string *msg) {
+  const int64_t n = g.n, nnz = g.nnz;
+  const int64_t *rp = g.row_ptr;
+  const int32_t *col = g.col;
+  const int8_t *w = g.w;
+  // structure
+  if (rp[0] != 0) { *msg = "row_ptr[0] != 0 (" + at(0, -1) + ")"; return kPrepGraph; }
+  for (int64_t v = 0; v < n; ++v)
+    if (rp[v + 1] < rp[v]) { *msg = "row_ptr decreases at " + at(v, -1); return kPrepGraph; }
+  if (rp[n] != nnz) { *msg = "row_ptr[n] != nnz (" + at(n, -1) + ")"; return kPrepGraph; }
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k)
+      if (col[k] < 0 || col[k] >= n) { *msg = "column out of range at " + at(v, k); return kPrepGraph; }
+  // self-loops
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k)
+      if (col[k] == v) { *msg = "self-loop at " + at(v, k); return kPrepSelfLoop; }
+  try {
+    // duplicate neighbours: stamp[u] = v + 1 once u has been seen in row v
+    std::vector<int64_t> stamp(n, 0);
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
+        if (stamp[col[k]] == v + 1) { *msg = "duplicate neighbour at " + at(v, k); return kPrepDuplicate; }
+        stamp[col[k]] = v + 1;
+      }
+    // symmetry: the transpose lists, for each row v, the (x, w) with x -> v.
+    // Entry (v -> u, w) has its reverse iff (u, w) is in transpose row v.
+    std::vector<int64_t> tp(n + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) ++tp[col[k] + 1];
+    for (int64_t v = 0; v < n; ++v) tp[v + 1] += tp[v];
+    std::vector<int32_t> tsrc(nnz);
+    std::vector<int8_t> tw(nnz);
+    {
+      std::vector<int64_t> fill(tp.begin(), tp.end() - 1);
+      for (int64_t v = 0; v < n; ++v)
+        for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
+          int64_t pos = fill[col[k]]++;
+          tsrc[pos] = (int32_t)v;
+          tw[pos] = w[k];
+        }
+    }
+    std::vector<int16_t> mark_w(n, 0);
+    std::fill(stamp.begin(), stamp.end(), 0);
+    for (int64_t v = 0; v < n; ++v) {
+      for (int64_t q = tp[v]; q < tp[v + 1]; ++q) {
+        stamp[tsrc[q]] = v + 1;
+        mark_w[tsrc[q]] = tw[q];
+      }
+      for (int64_t k = rp[v]; k < rp[v + 1]; ++k)
+        if (stamp[col[k]] != v + 1 || mark_w[col[k]] != w[k]) {
+          *msg = "edge without an equal-weight reverse at " + at(v, k);
+          return kPrepAsymmetric;
+        }
+    }
+  } catch (const std::bad_alloc &) {
+    *msg = "host allocation failed during validation";
+    return kPrepNoMem;
+  }
+  // field range
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t s = 0;
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) s += w[k] < 0 ? -(int64_t)w[k] : (int64_t)w[k];
+    if (s > (int64_t)std::numeric_limits<int32_t>::max()) {
+      *msg = "sum of |w| exceeds INT32_MAX at " + at(v, -1);
+      return kPrepOverflow;
+    }
+  }
+  int64_t W = 0;
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k)
+      if (col[k] > v) W += w[k];
+  *W_out = W;
+  return kPrepOk;
+}
+
+int32_t greedy_coloring(const HostCSR &g, bool largest_first, std::vector<int32_t> *color) {
+  const int64_t n = g.n;
+  const int64_t *rp = g.row_ptr;
+  color->assign(n, -1);
+  std::vector<int32_t> visit(n);
+  int64_t maxdeg = 0;
+  for (int64_t v = 0; v < n; ++v) maxdeg = std::max(maxdeg, rp[v + 1] - rp[v]);
+  if (largest_first) {
+    // counting sort by degree, descending; ids ascending inside a degree
+    std::vector<int64_t> start(maxdeg + 2, 0);
+    for (int64_t v = 0; v < n; ++v) ++start[maxdeg - (rp[v + 1] - rp[v]) + 1];
+    for (int64_t d = 0; d <= maxdeg; ++d) start[d + 1] += start[d];
+    for (int64_t v = 0; v < n; ++v) visit[start[maxdeg - (rp[v + 1] - rp[v])]++] = (int32_t)v;
+  } else {
+    for (int64_t v = 0; v < n; ++v) visit[v] = (int32_t)v;
+  }
+  std::vector<int64_t> taken(maxdeg + 2, -1);
+  int32_t n_colors = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t v = visit[i];
+    const int64_t deg = rp[v + 1] - rp[v];
+    for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
+      const int32_t c = (*color)[g.col[k]];
+      if (c >= 0 && c <= deg) taken[c] = v;
+    }
+    int32_t c = 0;
+    while (taken[c] == v) ++c;
+    (*color)[v] = c;
+    n_colors = std::max(n_colors, c + 1);
+  }
+  return n_colors;
+}
+
+int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors,
+                 int64_t long_deg, HostLayout *out, std::string *msg) {
+  HostLayout &L = *out;
+  const int64_t n = g.n;
+  const int64_t *rp = g.row_ptr;
+  try {
+    L.pm1 = true;
+    for (int64_t k = 0; k < g.nnz; ++k)
+      if (g.w[k] != 1 && g.w[k] != -1) { L.pm1 = false; break; }
+    L.n_phases = n_colors;
+    // vertices of each class, by (degree desc, id asc)
+    std::vector<int64_t> cnt(n_colors + 1, 0);
+    for (int64_t v = 0; v < n; ++v) ++cnt[color[v] + 1];
+    for (int32_t c = 0; c < n_colors; ++c) cnt[c + 1] += cnt[c];
+    std::vector<int32_t> byc(n);
+    {
+      std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+      for (int64_t v = 0; v < n; ++v) byc[fill[color[v]]++] = (int32_t)v;
+    }
+    auto deg = [&](int32_t v) { return rp[v + 1] - rp[v]; };
+    for (int32_t c = 0; c < n_colors; ++c)
+      std::stable_sort(byc.begin() + cnt[c], byc.begin() + cnt[c + 1],
+                       [&](int32_t a, int32_t b) { return deg(a) > deg(b); });
+    // slots: each class padded to a multiple of 64
+    L.cls_begin.assign(n_colors + 1, 0);
+    for (int32_t c = 0; c < n_colors; ++c) {
+      const int64_t size = cnt[c + 1] - cnt[c];
+      L.cls_begin[c + 1] = L.cls_begin[c] + (size + kSliceRows - 1) / kSliceRows * kSliceRows;
+    }
+    L.n_slots = L.cls_begin[n_colors];
+    if (L.n_slots >= (int64_t)0x7FFFFFFF) { *msg = "too many vertices"; return kPrepArg; }
+    L.vid.assign(L.n_slots, -1);
+    L.slot_of.assign(n, -1);
+    for (int32_t c = 0; c < n_colors; ++c)
+      for (int64_t i = cnt[c]; i < cnt[c + 1]; ++i) {
+        const int64_t slot = L.cls_begin[c] + (i - cnt[c]);
+        L.vid[slot] = byc[i];
+        L.slot_of[byc[i]] = (int32_t)slot;
+      }
+    // items and entry offsets
+    L.items.clear();
+    L.phase_items.assign(n_colors + 1, 0);
+    uint64_t chunks = 0;  // uint4 chunks allocated so far
+    for (int32_t c = 0; c < n_colors; ++c) {
+      for (int64_t s0 = L.cls_begin[c]; s0 < L.cls_begin[c + 1]; s0 += kSliceRows) {
+        const int32_t first = L.vid[s0];
+        const int64_t dmax = first >= 0 ? deg(first) : 0;
+        if (dmax > long_deg) {
+          for (int64_t r = s0; r < s0 + kSliceRows; ++r) {
+            if (L.vid[r] < 0) continue;
+            const uint64_t len4 = (uint64_t)(deg(L.vid[r]) + 3) / 4;
+            L.items.push_back(Item{(uint32_t)r, (uint32_t)chunks, (uint32_t)len4, kItemLong});
+            L.max_long_len4 = std::max<int64_t>(L.max_long_len4, (int64_t)len4);
+            chunks += len4;
+          }
+        } else {
+          const uint64_t len4 = (uint64_t)(dmax + 3) / 4;
+          L.items.push_back(Item{(uint32_t)(s0 / kSliceRows), (uint32_t)chunks, (uint32_t)len4, kItemSlice});
+          chunks += len4 * kSliceRows;
+        }
+        if (chunks >= (uint64_t)0xFFFFFFFFu) { *msg = "edge stream too large"; return kPrepArg; }
+      }
+      L.phase_items[c + 1] = (uint32_t)L.items.size();
+    }
+    // fill the entry stream
+    const uint32_t pad = L.pm1 ? kSentinel : 0u;
+    L.entries.assign(chunks * 4, pad);
+    if (!L.pm1) L.wts.assign(chunks * 4, 0);
+    auto put = [&](uint64_t pos, int64_t k) {
+      const uint32_t slot = (uint32_t)L.slot_of[g.col[k]];
+      if (L.pm1) {
+        L.entries[pos] = slot | (g.w[k] < 0 ? kSignBit : 0u);
+      } else {
+        L.entries[pos] = slot;
+        L.wts[pos] = g.w[k];
+      }
+    };
+    for (const Item &it : L.items) {
+      if (it.kind == kItemLong) {
+        const int32_t v = L.vid[it.id];
+        uint64_t pos = (uint64_t)it.base4 * 4;
+        for (int64_t k = rp[v]; k < rp[v + 1]; ++k) put(pos++, k);
+      } else {
+        for (int lane = 0; lane < kSliceRows; ++lane) {
+          const int32_t v = L.vid[(int64_t)it.id * kSliceRows + lane];
+          if (v < 0) continue;
+          int64_t q = 0;
+          for (int64_t k = rp[v]; k < rp[v + 1]; ++k, ++q) {
+            const uint64_t chunk = (uint64_t)it.base4 + (uint64_t)(q / 4) * kSliceRows + lane;
+            put(chunk * 4 + (q % 4), k);
+          }
+        }
+      }
+    }
+  } catch (const std::bad_alloc &) {
+    *msg = "host allocation failed while building the layout";
+    return kPrepNoMem;
+  }
+  return kPrepOk;
+}
+
+std::vector<uint32_t> partition_waves(const HostLayout &L, int32_t nw) {
+  std::vector<uint32_t> out((size_t)L.n_phases * (nw + 1));
+  for (int32_t p = 0; p < L.n_phases; ++p) {
+    const uint32_t b = L.phase_items[p], e = L.phase_items[p + 1];
+    std::vector<uint64_t> prefix(e - b + 1, 0);
+    for (uint32_t i = b; i < e; ++i) {
+      const Item &it = L.items[i];
+      const uint64_t cost = 64 + (uint64_t)it.len4 * (it.kind == kItemSlice ? 4 * kSliceRows : 4);
+      prefix[i - b + 1] = prefix[i - b] + cost;
+    }
+    const uint64_t total = prefix.back();
+    uint32_t *o = &out[(size_t)p * (nw + 1)];
+    uint32_t j = 0;
+    for (int32_t w = 0; w <= nw; ++w) {
+      // first item whose cost prefix reaches w/nw of the phase
+      const unsigned __int128 goal = (unsigned __int128)total * (uint64_t)w;
+      while (j < e - b && (unsigned __int128)prefix[j] * (uint64_t)nw < goal) ++j;
+      o[w] = b + j;
+    }
+    o[nw] = e;
+  }
+  return out;
+}
+
+bool check_layout(const HostLayout &L, std::string *msg) {
+  const uint64_t chunks = L.entries.size() / 4;
+  for (size_t i = 0; i < L.items.size(); ++i) {
+    const Item &it = L.items[i];
+    bool ok;
+    if (it.kind == kItemSlice)
+      ok = ((int64_t)it.id + 1) * kSliceRows <= L.n_slots &&
+           (uint64_t)it.base4 + (uint64_t)it.len4 * kSliceRows <= chunks;
+    else
+      ok = (int64_t)it.id < L.n_slots && (uint64_t)it.base4 + it.len4 <= chunks &&
+           L.vid[it.id] >= 0;
+    if (!ok) {
+      *msg = "layout item " + std::to_string(i) + " out of range";
+      return false;
+    }
+  }
+  for (size_t k = 0; k < L.entries.size(); ++k) {
+    const uint32_t x = L.entries[k];
+    if (L.pm1 && x == kSentinel) continue;
+    const uint32_t slot = L.pm1 ? (x & ~kSignBit) : x;
+    if ((int64_t)slot >= L.n_slots || L.vid[slot] < 0) {
+      *msg = "layout entry " + std::to_string(k) + " names a bad slot";
+      return false;
+    }
+  }
+  for (int32_t p = 0; p < L.n_phases; ++p)
+    if (L.cls_begin[p] % kSliceRows != 0 || L.phase_items[p] > L.phase_items[p + 1]) {
+      *msg = "layout class table inconsistent";
+      return false;
+    }
+  return true;
+}
+
+}  // namespace ising

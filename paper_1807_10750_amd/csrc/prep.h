@@ -1,0 +1,69 @@
+// prep.h -- host preparation of a graph handle: validation, colouring,
+// renumbering into slots and the sliced edge layout (internal).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "layout.h"
+
+namespace ising {
+
+// Status values mirror ising_status_t.
+enum PrepStatus {
+  kPrepOk = 0,
+  kPrepArg = 1,
+  kPrepGraph = 2,
+  kPrepSelfLoop = 3,
+  kPrepDuplicate = 4,
+  kPrepAsymmetric = 5,
+  kPrepOverflow = 6,
+  kPrepNoMem = 7,
+};
+
+struct HostCSR {
+  int64_t n = 0, nnz = 0;
+  const int64_t *row_ptr = nullptr;
+  const int32_t *col = nullptr;
+  const int8_t *w = nullptr;
+};
+
+// Checks, in order: structure, self-loops, duplicate neighbours, symmetry of
+// (u, v, w), int32 range of every row's sum |w|.  On failure returns the
+// status and writes a message naming the offending row and entry.
+int validate_graph(const HostCSR &g, int64_t *W_out, std::string *msg);
+
+// Greedy colouring: vertices visited by id (largest_first = false) or by
+// (degree desc, id asc); each takes the least colour absent from its
+// already-coloured neighbours.
+int32_t greedy_coloring(const HostCSR &g, bool largest_first, std::vector<int32_t> *color);
+
+struct HostLayout {
+  int64_t n_slots = 0;                 // multiple of 64
+  int32_t n_phases = 0;                // colour classes
+  bool pm1 = false;                    // every weight is +1 or -1
+  std::vector<int32_t> vid;            // slot -> vertex (-1 = padding)
+  std::vector<int32_t> slot_of;        // vertex -> slot
+  std::vector<int64_t> cls_begin;      // [n_phases + 1] first slot of each class
+  std::vector<uint32_t> entries;       // edge stream, multiple of 4 entries
+  std::vector<int8_t> wts;             // per entry (general weights only)
+  std::vector<Item> items;             // phase by phase
+  std::vector<uint32_t> phase_items;   // [n_phases + 1]
+  int64_t max_long_len4 = 0;
+};
+
+// long_deg: rows of a slice whose largest degree exceeds it become
+// wavefront-per-row items.
+int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors,
+                 int64_t long_deg, HostLayout *out, std::string *msg);
+
+// Splits each phase's items over nw wavefronts in contiguous runs of about
+// equal cost.  Returns [n_phases][nw + 1] item offsets.
+std::vector<uint32_t> partition_waves(const HostLayout &L, int32_t nw);
+
+// Verifies that every item addresses only memory inside the layout (index
+// ranges of entries, slots and spin words).  Returns false with a message.
+bool check_layout(const HostLayout &L, std::string *msg);
+
+}  // namespace ising

@@ -1,0 +1,59 @@
+"""The C-ABI library loads and exports every function include/ising.h declares
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ising.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:ising_status_t|const char \*)\s*(ising[A-Za-z]+)\s*\(", text, re.M)))
+
+
+def _lib_path():
+    from paper_1807_10750_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    return build.LIB
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("isingCreate", "isingAnneal", "isingCut", "isingDestroy", "isingLastError"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib_path())
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_uses_the_c_names():
+    from paper_1807_10750_amd import ising
+    assert sorted(ising.EXPORTED) == declared()
+    for n in declared():
+        assert hasattr(ising, n) or n == "isingLastError"
+
+
+def test_last_error_is_empty_string_initially():
+    lib = ctypes.CDLL(_lib_path())
+    lib.isingLastError.restype = ctypes.c_char_p
+    assert lib.isingLastError() == b""
+
+
+def test_null_handle_arguments_are_rejected_without_a_device():
+    lib = ctypes.CDLL(_lib_path())
+    lib.isingDestroy.argtypes = [ctypes.c_void_p]
+    assert lib.isingDestroy(None) == 0
+    lib.isingCreate.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int32,
+                                ctypes.c_void_p]
+    assert lib.isingCreate(None, 4, 0, None, None, None, 0, 1, None) == 1
+    h = ctypes.c_void_p()
+    assert lib.isingCreate(ctypes.byref(h), -1, 0, None, None, None, 0, 1, None) == 1
+    lib.isingCut.argtypes = [ctypes.c_void_p] * 4
+    assert lib.isingCut(None, None, None, None) == 1

@@ -29,7 +29,10 @@
  *   R5  F_p schedule: integer thresholds T_t; flip iff a 32-bit uniform
  *       x < T_t.  p -> T = min(2^32-1, floor(p * 2^32)), linear in t.
  *   R6  Exactly M sweeps; the last linear threshold is T_end.
- *   R7  RNG: Philox4x32-10, word 0, counter {v, t, r, 0}, key = seed.
+ *   R7  RNG: Philox4x32-10 with key = seed.  The draw of vertex v, sweep t,
+ *       replica r is word (r mod 4) of the block at counter {v, t, r div 4, 0},
+ *       so one block serves four replicas (the paper only asks for one
+ *       independent uniform per spin and sweep).
  *   R8  The RNG is keyed by the caller's vertex id.
  *   R9  Each unordered edge counted once in W, E and the cut.
  *   R10 Self-loops and duplicate edges are rejected; int8 weights; the
@@ -87,13 +90,15 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Word 0 of Philox4x32-10 at counter {a, b, c, d}, key {lo(seed), hi(seed)}. */
-static uint32_t philox_word0(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint64_t seed) {
-  uint32_t ctr[4] = {a, b, c, d};
+/* The 32-bit draw of vertex v, sweep (or domain-0 index) t, replica r in
+ * counter domain d: word (r mod 4) of Philox4x32-10 at counter
+ * {v, t, r div 4, d}, key {lo(seed), hi(seed)} (reading R7). */
+static uint32_t draw(uint32_t v, uint32_t t, uint32_t r, uint32_t d, uint64_t seed) {
+  uint32_t ctr[4] = {v, t, r / 4u, d};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t out[4];
   oracle_philox4x32_10(ctr, key, out);
-  return out[0];
+  return out[r % 4u];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -257,13 +262,13 @@ void oracle_order(int64_t n, const int32_t *color, int32_t n_colors, int32_t *or
 }
 
 /* ------------------------------------------------------------------------ */
-/* Initial spins (reading R3): s = +1 if bit 31 of Philox({v,0,r,1}) is set. */
+/* Initial spins (reading R3): s = +1 if bit 31 of the domain-1 draw is set. */
 /* spins is [R][n].                                                         */
 /* ------------------------------------------------------------------------ */
 void oracle_init_spins(int64_t n, int32_t R, uint64_t seed, int8_t *spins) {
   for (int32_t r = 0; r < R; ++r)
     for (int64_t v = 0; v < n; ++v) {
-      uint32_t x = philox_word0((uint32_t)v, 0u, (uint32_t)r, 1u, seed);
+      uint32_t x = draw((uint32_t)v, 0u, (uint32_t)r, 1u, seed);
       spins[(int64_t)r * n + v] = (x >> 31) ? 1 : -1;
     }
 }
@@ -289,7 +294,7 @@ static int8_t local_update(int32_t h, int8_t s) {
 /* by a sequential visit in the given order (the (colour, id) order makes   */
 /* this equal to any colour-phased parallel execution).  For each sweep t   */
 /* in [t_begin, t_end): update each vertex from its local field, then flip  */
-/* it when Philox({v,t,r,0}) < T[t] (R4, R5, R7).  T holds the whole        */
+/* it when its domain-0 draw is below T[t] (R4, R5, R7).  T holds the whole */
 /* schedule (indexed by absolute sweep).                                    */
 /* ------------------------------------------------------------------------ */
 int oracle_anneal(int64_t n, const int64_t *row_ptr, const int32_t *col, const int8_t *w,
@@ -303,7 +308,7 @@ int oracle_anneal(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
         int64_t v = order[i];
         int32_t h = local_field(v, row_ptr, col, w, s);
         s[v] = local_update(h, s[v]);
-        if (philox_word0((uint32_t)v, (uint32_t)t, (uint32_t)r, 0u, seed) < T[t]) s[v] = (int8_t)-s[v];
+        if (draw((uint32_t)v, (uint32_t)t, (uint32_t)r, 0u, seed) < T[t]) s[v] = (int8_t)-s[v];
       }
     }
   }
@@ -324,7 +329,7 @@ int oracle_anneal_jacobi(int64_t n, const int64_t *row_ptr, const int32_t *col, 
       for (int64_t v = 0; v < n; ++v) {
         int32_t h = local_field(v, row_ptr, col, w, prev);
         int8_t x = local_update(h, prev[v]);
-        if (philox_word0((uint32_t)v, (uint32_t)t, (uint32_t)r, 0u, seed) < T[t]) x = (int8_t)-x;
+        if (draw((uint32_t)v, (uint32_t)t, (uint32_t)r, 0u, seed) < T[t]) x = (int8_t)-x;
         s[v] = x;
       }
     }

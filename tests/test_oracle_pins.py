@@ -49,25 +49,27 @@ def test_philox_matches_aten(aten_philox):
 
 
 def test_init_spins_use_domain1_bit31(aten_philox):
-    # s_v = +1 iff bit 31 of word 0 at counter {v, 0, r, 1}, key = seed.
+    # s_v = +1 iff bit 31 of word (r mod 4) at counter {v, 0, r div 4, 1}, key = seed.
     seed = 0x0123456789ABCDEF
-    n, R = 50, 3
-    rows = [[v, 0, r, 1, seed & 0xFFFFFFFF, seed >> 32] for r in range(R) for v in range(n)]
-    ref = aten_philox(rows)[:, 0].reshape(R, n)
+    n, R = 50, 7
+    rows = [[v, 0, r // 4, 1, seed & 0xFFFFFFFF, seed >> 32] for r in range(R) for v in range(n)]
+    ref = aten_philox(rows)[np.arange(R * n), np.repeat(np.arange(R) % 4, n)].reshape(R, n)
     expect = np.where(ref >> 31, 1, -1).astype(np.int8)
     assert np.array_equal(O.init_spins(n, R, seed), expect)
 
 
 def test_isolated_vertices_flip_by_counter(aten_philox):
     # With no edges the field is 0, the update keeps the spin, and only the
-    # random flips act: spin_v(end) = s0_v * prod_t (-1 if x(v,t,r) < T[t]).
-    n, R, M, seed = 9, 2, 30, 991
+    # random flips act: spin_v(end) = s0_v * prod_t (-1 if x(v,t,r) < T[t]),
+    # x = word (r mod 4) of the block at counter {v, t, r div 4, 0}.
+    n, R, M, seed = 9, 6, 30, 991
     g = G.empty(n)
     T = O.thresholds(0.9, 0.2, M)
     s0 = G.random_spins(n, R, 5)
-    rows = [[v, t, r, 0, seed & 0xFFFFFFFF, seed >> 32]
+    rows = [[v, t, r // 4, 0, seed & 0xFFFFFFFF, seed >> 32]
             for r in range(R) for v in range(n) for t in range(M)]
-    x = aten_philox(rows)[:, 0].reshape(R, n, M)
+    words = np.repeat(np.arange(R) % 4, n * M)
+    x = aten_philox(rows)[np.arange(R * n * M), words].reshape(R, n, M)
     flips = (x < T[None, None, :].astype(np.uint64)).sum(axis=2)
     expect = (s0 * np.where(flips % 2 == 1, -1, 1)).astype(np.int8)
     col, nc = O.color(g)
@@ -80,7 +82,7 @@ def test_flip_needs_draw_strictly_below_threshold(aten_philox):
     # false there, so that sweep must not flip it; T = x + 1 must flip it.
     seed, t = 12345, 3
     g = G.empty(1)
-    x = int(aten_philox([[0, t, 0, 0, seed & 0xFFFFFFFF, seed >> 32]])[0, 0])
+    x = int(aten_philox([[0, t, 0, 0, seed & 0xFFFFFFFF, seed >> 32]])[0, 0])  # replica 0: word 0
     col, nc = O.color(g)
     o = O.order(col, nc)
     s0 = np.ones((1, 1), np.int8)

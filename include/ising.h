@@ -163,6 +163,7 @@ typedef struct {
   int32_t grid;             /* workgroups of the anneal launch */
   int32_t block;            /* threads per workgroup */
   int32_t pm1;              /* 1 if every weight is +-1 (sign packed into the edge entry) */
+  int32_t encoding;         /* edge entry encoding: 0 slot|sign, 1 slot|int8 weight, 2 slot + weight stream */
   int64_t edge_bytes;       /* bytes of the edge stream read once per sweep per group */
   int64_t vertex_bytes;     /* bytes of per-vertex data read once per sweep per group */
   int64_t spin_bytes;       /* bytes of one group's packed spin state */

@@ -95,12 +95,13 @@ struct ising_graph_s {
   uint32_t *d_wts4 = nullptr;
   int32_t *d_vid = nullptr;
   Item *d_items = nullptr;
-  uint32_t *d_wave_ptr = nullptr;
-  uint32_t *d_cls_w64 = nullptr;
+  uint32_t *d_wave_ptr[2] = {nullptr, nullptr};  // per mode: [phases][nw + 1]
+  uint32_t *d_cls_w64[2] = {nullptr, nullptr};   // per mode: phase -> spin word range
+  int32_t n_phases[2] = {0, 0};
   uint32_t *d_spins = nullptr;
   uint32_t *d_thr = nullptr;
   int64_t thr_cap = 0;
-  uint32_t *d_bar = nullptr;   // [0] barrier counter, [1] anneal error flag, [2] spin-check flag
+  uint32_t *d_bar = nullptr;   // barrier counters, error and spin-check flags (kBar*)
   unsigned long long *d_cut = nullptr;
   int8_t *d_stage = nullptr;
   // schedule cache
@@ -126,7 +127,8 @@ ising_status_t dev_alloc(T **p, size_t bytes, const char *what) {
 }
 
 void free_all(ising_graph_s *g) {
-  void *bufs[] = {g->d_entries, g->d_wts4, g->d_vid, g->d_items, g->d_wave_ptr, g->d_cls_w64,
+  void *bufs[] = {g->d_entries, g->d_wts4, g->d_vid, g->d_items, g->d_wave_ptr[0], g->d_wave_ptr[1],
+                  g->d_cls_w64[0], g->d_cls_w64[1],
                   g->d_spins, g->d_thr, g->d_bar, g->d_cut, g->d_stage};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -217,7 +219,7 @@ ising_status_t check_flags(ising_graph_s *g, hipStream_t st) {
   uint32_t flags[3] = {0, 0, 0};
   HIP_TRY(hipMemcpyAsync(flags, g->d_bar, sizeof flags, hipMemcpyDeviceToHost, st), "flag readback");
   HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-  if (flags[1] != 0) return fail(ISING_ERR_DEVICE, "an anneal grid barrier timed out");
+  if (flags[kBarErr] != 0) return fail(ISING_ERR_DEVICE, "an anneal grid barrier timed out");
   return ISING_OK;
 }
 
@@ -277,19 +279,24 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   } catch (const std::bad_alloc &) {
     return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed while colouring"));
   }
-  const int64_t long_deg = std::max<int64_t>(4, env_int("ISING_LONG_DEG", 64));
-  v = build_layout(csr, g->color, g->n_colors, long_deg, &g->lay, &msg);
-  if (v != kPrepOk) return bail(fail((ising_status_t)v, msg));
-  if (!check_layout(g->lay, &msg)) return bail(fail(ISING_ERR_DEVICE, "internal layout check: " + msg));
-  HostLayout &lay = g->lay;
-
   // replica packing: as many replicas per pass as fit an LDS copy of the state
+  int64_t n_slots = 0;
+  std::vector<int64_t> class_size(g->n_colors, 0);
+  for (int64_t v = 0; v < n; ++v) ++class_size[g->color[v]];
+  for (int64_t c : class_size) n_slots += (c + 63) / 64 * 64;
   int L = pow2_at_least(n_replicas);
   const bool allow_lds = env_int("ISING_NO_LDS", 0) == 0;
-  auto state_bytes = [&](int l) { return (size_t)lay.n_slots * (size_t)l / 8; };
+  auto state_bytes = [&](int l) { return (size_t)n_slots * (size_t)l / 8; };
   while (allow_lds && L > 1 && state_bytes(L) > kLdsBudget) L >>= 1;
   g->use_lds = allow_lds && state_bytes(L) <= kLdsBudget;
   if (!g->use_lds) L = pow2_at_least(n_replicas);
+  const int bin_shift = (int)std::min<int64_t>(8, std::max<int64_t>(0, env_int("ISING_BIN_SHIFT", 0)));
+  int enc = choose_encoding(csr, n_slots);
+  if (enc == kEncW8 && env_int("ISING_WIDE", 0) != 0) enc = kEncWide;
+  v = build_layout(csr, g->color, g->n_colors, enc, kmax_for(L, enc), bin_shift, &g->lay, &msg);
+  if (v != kPrepOk) return bail(fail((ising_status_t)v, msg));
+  if (!check_layout(g->lay, &msg)) return bail(fail(ISING_ERR_DEVICE, "internal layout check: " + msg));
+  HostLayout &lay = g->lay;
   g->L = L;
   g->n_groups = (n_replicas + L - 1) / L;
   g->n_words = (uint32_t)((size_t)lay.n_slots * (size_t)L / 32);
@@ -298,7 +305,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   // grid: enough workgroups for the largest colour class, at most what is co-resident
   int per_cu = 0;
   {
-    hipError_t e = anneal_occupancy(L, lay.pm1, g->use_lds, g->lds_bytes, &per_cu);
+    hipError_t e = anneal_occupancy(L, lay.enc, g->use_lds, g->lds_bytes, &per_cu);
     if (e != hipSuccess) return bail(hip_fail(e, "occupancy query"));
   }
   hipDeviceProp_t prop;
@@ -312,20 +319,28 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   for (int32_t p = 0; p < lay.n_phases; ++p)
     max_phase = std::max(max_phase, lay.phase_items[p + 1] - lay.phase_items[p]);
   int grid = (int)std::min<int64_t>(max_grid, std::max<int64_t>(1, (max_phase + waves_per_block - 1) / waves_per_block));
+  if ((int64_t)lay.items.size() <= 4 * waves_per_block) grid = 1;  // no grid barriers for tiny graphs
   const int64_t want = env_int("ISING_GRID", 0);
   if (want > 0) grid = (int)std::min<int64_t>(want, max_grid);
   g->grid = grid;
   g->nw = grid * waves_per_block;
-  std::vector<uint32_t> wave_ptr = partition_waves(lay, g->nw);
-  std::vector<uint32_t> cls_w64(lay.n_phases + 1);
-  for (int32_t p = 0; p <= lay.n_phases; ++p) cls_w64[p] = (uint32_t)((uint64_t)lay.cls_begin[p] * L / 64);
+  // phase tables: deterministic = one colour class per phase; async merges small classes
+  std::vector<uint32_t> wave_ptr[2], cls_w64[2];
+  const int merge_div = (int)env_int("ISING_ASYNC_MERGE", 32);
+  for (int m = 0; m < 2; ++m) {
+    const std::vector<int32_t> pc = phase_classes(lay, class_size, m == 0 ? 0 : merge_div);
+    g->n_phases[m] = (int32_t)pc.size() - 1;
+    wave_ptr[m] = partition_waves(lay, pc, g->nw);
+    cls_w64[m].resize(pc.size());
+    for (size_t p = 0; p < pc.size(); ++p) cls_w64[m][p] = (uint32_t)((uint64_t)lay.cls_begin[pc[p]] * L / 64);
+  }
 
   // device buffers
   const size_t entry_b = lay.entries.size() * sizeof(uint32_t);
   g->entry_bytes = (int64_t)entry_b + (int64_t)lay.wts.size();
   if ((r = dev_alloc(&g->d_entries, entry_b, "edge stream")) != ISING_OK) return bail(r);
   if ((r = upload(g->d_entries, lay.entries.data(), entry_b, "edge stream upload")) != ISING_OK) return bail(r);
-  if (!lay.pm1) {
+  if (lay.enc == kEncWide) {
     if ((r = dev_alloc(&g->d_wts4, lay.wts.size(), "weights")) != ISING_OK) return bail(r);
     if ((r = upload(g->d_wts4, lay.wts.data(), lay.wts.size(), "weights upload")) != ISING_OK) return bail(r);
   }
@@ -333,17 +348,21 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   if ((r = upload(g->d_vid, lay.vid.data(), sizeof(int32_t) * lay.vid.size(), "slot upload")) != ISING_OK) return bail(r);
   if ((r = dev_alloc(&g->d_items, sizeof(Item) * lay.items.size(), "items")) != ISING_OK) return bail(r);
   if ((r = upload(g->d_items, lay.items.data(), sizeof(Item) * lay.items.size(), "items upload")) != ISING_OK) return bail(r);
-  if ((r = dev_alloc(&g->d_wave_ptr, sizeof(uint32_t) * wave_ptr.size(), "wave table")) != ISING_OK) return bail(r);
-  if ((r = upload(g->d_wave_ptr, wave_ptr.data(), sizeof(uint32_t) * wave_ptr.size(), "wave upload")) != ISING_OK) return bail(r);
-  if ((r = dev_alloc(&g->d_cls_w64, sizeof(uint32_t) * cls_w64.size(), "class table")) != ISING_OK) return bail(r);
-  if ((r = upload(g->d_cls_w64, cls_w64.data(), sizeof(uint32_t) * cls_w64.size(), "class upload")) != ISING_OK) return bail(r);
+  for (int m = 0; m < 2; ++m) {
+    if ((r = dev_alloc(&g->d_wave_ptr[m], sizeof(uint32_t) * wave_ptr[m].size(), "wave table")) != ISING_OK) return bail(r);
+    if ((r = upload(g->d_wave_ptr[m], wave_ptr[m].data(), sizeof(uint32_t) * wave_ptr[m].size(), "wave upload")) != ISING_OK)
+      return bail(r);
+    if ((r = dev_alloc(&g->d_cls_w64[m], sizeof(uint32_t) * cls_w64[m].size(), "class table")) != ISING_OK) return bail(r);
+    if ((r = upload(g->d_cls_w64[m], cls_w64[m].data(), sizeof(uint32_t) * cls_w64[m].size(), "class upload")) != ISING_OK)
+      return bail(r);
+  }
   if ((r = dev_alloc(&g->d_spins, sizeof(uint32_t) * (size_t)g->n_words * g->n_groups, "spins")) != ISING_OK) return bail(r);
-  if ((r = dev_alloc(&g->d_bar, sizeof(uint32_t) * 4, "flags")) != ISING_OK) return bail(r);
+  if ((r = dev_alloc(&g->d_bar, sizeof(uint32_t) * kBarWords, "flags")) != ISING_OK) return bail(r);
   if ((r = dev_alloc(&g->d_cut, sizeof(unsigned long long) * 2 * (size_t)n_replicas + 16, "cut")) != ISING_OK) return bail(r);
   if ((r = dev_alloc(&g->d_stage, (size_t)n * (size_t)n_replicas, "spin staging")) != ISING_OK) return bail(r);
   {
     hipError_t e = launch_fill_u32(g->d_spins, g->n_words * (uint32_t)g->n_groups, 0xFFFFFFFFu, st);
-    if (e == hipSuccess) e = launch_fill_u32(g->d_bar, 4, 0u, st);
+    if (e == hipSuccess) e = launch_fill_u32(g->d_bar, kBarWords, 0u, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bail(hip_fail(e, "initialising spins"));
   }
@@ -373,7 +392,8 @@ ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info) {
   info->uses_lds = g->use_lds ? 1 : 0;
   info->grid = g->grid;
   info->block = kAnnealBlock;
-  info->pm1 = g->lay.pm1 ? 1 : 0;
+  info->pm1 = g->lay.enc == kEncPm1 ? 1 : 0;
+  info->encoding = g->lay.enc;
   info->edge_bytes = g->entry_bytes;
   info->vertex_bytes = (int64_t)g->lay.n_slots * 4;
   info->spin_bytes = (int64_t)g->n_words * 4;
@@ -419,10 +439,10 @@ ising_status_t isingSetSpins(ising_graph_t g, const int8_t *spins, void *stream)
   const int64_t count = g->n * (int64_t)g->R;
   const int8_t *src = spins;
   if (is_device_ptr(spins)) {
-    HIP_TRY(launch_fill_u32(g->d_bar + 2, 1, 0u, st), "flag reset");
-    HIP_TRY(launch_check_spins(spins, count, g->d_bar + 2, st), "spin check launch");
+    HIP_TRY(launch_fill_u32(g->d_bar + kBarCheck, 1, 0u, st), "flag reset");
+    HIP_TRY(launch_check_spins(spins, count, g->d_bar + kBarCheck, st), "spin check launch");
     uint32_t bad = 0;
-    HIP_TRY(hipMemcpyAsync(&bad, g->d_bar + 2, sizeof bad, hipMemcpyDeviceToHost, st), "flag readback");
+    HIP_TRY(hipMemcpyAsync(&bad, g->d_bar + kBarCheck, sizeof bad, hipMemcpyDeviceToHost, st), "flag readback");
     HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
     if (bad) return fail(ISING_ERR_INVALID_ARGUMENT, "spin values must be +1 or -1");
   } else {
@@ -488,19 +508,20 @@ ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *s, uint64_t 
   a.wts4 = g->d_wts4;
   a.vid = g->d_vid;
   a.items = g->d_items;
-  a.wave_ptr = g->d_wave_ptr;
-  a.cls_w64 = g->d_cls_w64;
+  const int m = mode == ISING_MODE_ASYNC ? 1 : 0;
+  a.wave_ptr = g->d_wave_ptr[m];
+  a.cls_w64 = g->d_cls_w64[m];
   a.thr = g->d_thr;
   a.bar = g->d_bar;
   a.n_words = g->n_words;
-  a.n_phases = g->lay.n_phases;
+  a.n_phases = g->n_phases[m];
   a.nw = g->nw;
   a.async_mode = mode == ISING_MODE_ASYNC ? 1 : 0;
   a.seed_lo = (uint32_t)seed;
   a.seed_hi = (uint32_t)(seed >> 32);
   a.spin_limit = (uint32_t)std::max<int64_t>(1000, env_int("ISING_BARRIER_POLLS", 20000000));
   // keep the barrier counter below 2^31 within one launch
-  const int64_t barriers_per_sweep = g->grid > 1 ? (a.async_mode ? 1 : std::max(1, g->lay.n_phases)) : 0;
+  const int64_t barriers_per_sweep = g->grid > 1 ? (a.async_mode ? 1 : std::max(1, a.n_phases)) : 0;
   int64_t chunk = sweep_end - sweep_begin;
   if (barriers_per_sweep > 0) chunk = std::max<int64_t>(1, ((int64_t)1 << 30) / (barriers_per_sweep * g->grid));
   for (int grp = 0; grp < g->n_groups; ++grp) {
@@ -510,8 +531,9 @@ ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *s, uint64_t 
     for (int64_t t0 = sweep_begin; t0 < sweep_end; t0 += chunk) {
       a.t_begin = t0;
       a.t_end = std::min(sweep_end, t0 + chunk);
-      HIP_TRY(launch_fill_u32(g->d_bar, 1, 0u, st), "barrier reset");
-      HIP_TRY(launch_anneal(g->L, g->lay.pm1, g->use_lds, a, g->grid, g->lds_bytes, st), "anneal launch");
+      HIP_TRY(launch_fill_u32(g->d_bar + kBarTop, 1, 0u, st), "barrier reset");
+      HIP_TRY(launch_fill_u32(g->d_bar + kBarGroup, kBarWords - kBarGroup, 0u, st), "barrier reset");
+      HIP_TRY(launch_anneal(g->L, g->lay.enc, g->use_lds, a, g->grid, g->lds_bytes, st), "anneal launch");
     }
   }
   return ISING_OK;
@@ -538,7 +560,7 @@ ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *st
       c.spins = g->d_spins + (size_t)grp * g->n_words;
       c.out = g->d_cut + 2 * (size_t)(grp * g->L + j);
       c.bit = j;
-      if (c.n_items > 0) HIP_TRY(launch_cut(g->L, g->lay.pm1, c, st), "cut launch");
+      if (c.n_items > 0) HIP_TRY(launch_cut(g->L, g->lay.enc, c, st), "cut launch");
     }
   if (dev_cut) {
     HIP_TRY(launch_cut_finalize(g->d_cut, g->R, cut, energy, st), "cut finalize");

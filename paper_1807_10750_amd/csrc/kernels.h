@@ -11,16 +11,16 @@ namespace ising {
 
 constexpr int kAnnealBlock = 1024;  // 16 wavefronts per workgroup
 
-hipError_t launch_anneal(int L, bool pm1, bool use_lds, const AnnealArgs &a, int grid, size_t lds_bytes,
+hipError_t launch_anneal(int L, int enc, bool use_lds, const AnnealArgs &a, int grid, size_t lds_bytes,
                          hipStream_t s);
-hipError_t anneal_occupancy(int L, bool pm1, bool use_lds, size_t lds_bytes, int *blocks_per_cu);
+hipError_t anneal_occupancy(int L, int enc, bool use_lds, size_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_randomize(int L, uint32_t *spins, const int32_t *vid, uint32_t n_words, uint32_t r0,
                             uint32_t r_count, uint64_t seed, hipStream_t s);
 hipError_t launch_set_spins(int L, uint32_t *spins, const int32_t *vid, uint32_t n_words, const int8_t *src,
                             int64_t n, uint32_t r0, uint32_t r_count, hipStream_t s);
 hipError_t launch_get_spins(int L, const uint32_t *spins, const int32_t *vid, uint32_t n_slots, int8_t *dst,
                             int64_t n, uint32_t r0, uint32_t r_count, hipStream_t s);
-hipError_t launch_cut(int L, bool pm1, const CutArgs &a, hipStream_t s);
+hipError_t launch_cut(int L, int enc, const CutArgs &a, hipStream_t s);
 hipError_t launch_check_spins(const int8_t *src, int64_t count, uint32_t *flag, hipStream_t s);
 hipError_t launch_cut_finalize(const unsigned long long *sums, int32_t R, int64_t *cut, int64_t *energy,
                                hipStream_t s);

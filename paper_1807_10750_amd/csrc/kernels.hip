@@ -4,15 +4,18 @@
 // 1807.10750): each spin takes the value that minimises its local energy
 // given its neighbours (Sec. II-A, Eq. 2, with J = -w so that low energy is
 // a large cut, Sec. III Eq. 4-5), then flips with the sweep's probability F_p
-// (Sec. IV-B, Algorithm 2).  Flip draws are Philox4x32-10 (Salmon et al.,
-// SC'11) word 0 at counter {vertex, sweep, replica, 0}, key = seed.
+// (Sec. IV-B, Algorithm 2).  Flip draws come from Philox4x32-10 (Salmon et
+// al., SC'11): replica r of vertex v in sweep t uses word (r mod 4) of the
+// block at counter {v, t, r div 4, 0}, key = seed.
 //
 // Work is issued colour class by colour class.  In deterministic mode a
 // grid barrier separates the classes, which makes the result equal to a
-// sequential sweep in (colour, id) order.  In async mode there is no barrier
-// inside a sweep: each workgroup refreshes a class's spins right after its
-// own share of that class and moves on, so a neighbour's value is from this
-// sweep or the previous one, as in the paper's unsynchronised update.
+// sequential sweep in (colour, id) order.  In async mode there is no wait
+// inside a sweep: each wavefront refreshes its share of a class's spins
+// right after its own items of that class and moves on, so a neighbour's
+// value is from this sweep or the previous one, as in the paper's
+// unsynchronised update.  Every wavefront keeps the loads of its next item
+// in flight while it computes the current one.
 //
 // Spin state is an L-bit mask per slot (replica bits) packed in uint32
 // words.  When it fits, each workgroup keeps a copy of the whole state in
@@ -29,9 +32,9 @@ namespace {
 
 constexpr int kWave = 64;
 
-// Philox4x32-10, word 0 only.
-__device__ __forceinline__ uint32_t philox_w0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                              uint32_t k0, uint32_t k1) {
+// Philox4x32-10 (Salmon et al., SC'11): the whole 4-word block.
+__device__ __forceinline__ uint4 philox4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                         uint32_t k1) {
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
     const uint32_t a_lo = 0xD2511F53u * c0;
@@ -45,7 +48,11 @@ __device__ __forceinline__ uint32_t philox_w0(uint32_t c0, uint32_t c1, uint32_t
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
-  return c0;
+  return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4 &x, uint32_t i) {
+  return i == 0 ? x.x : (i == 1 ? x.y : (i == 2 ? x.z : x.w));
 }
 
 __device__ __forceinline__ uint32_t ld_coherent(const uint32_t *p) {
@@ -73,11 +80,11 @@ __device__ __forceinline__ uint32_t mask_of(P words, uint32_t s) {
   return (words[bit >> 5] >> (bit & 31)) & lmask<L>();
 }
 
-// Adds the contribution of one edge entry to the L field accumulators.
-// pm1: entry = slot | sign; general: slot with separate weight w8.
-template <int L, bool PM1, typename P>
-__device__ __forceinline__ void accumulate(int32_t (&h)[L], uint32_t x, int32_t w8, P words) {
-  if (PM1) {
+// Adds the contribution of one edge entry to the L field accumulators
+// (entry encodings: see layout.h; wv is the separate weight of kEncWide).
+template <int L, int ENC, typename P>
+__device__ __forceinline__ void accumulate(int32_t (&h)[L], uint32_t x, int32_t wv, P words) {
+  if (ENC == kEncPm1) {
     const bool valid = x != kSentinel;
     const uint32_t slot = valid ? (x & ~kSignBit) : 0u;
     uint32_t m = mask_of<L>(words, slot);
@@ -85,28 +92,56 @@ __device__ __forceinline__ void accumulate(int32_t (&h)[L], uint32_t x, int32_t 
 #pragma unroll
     for (int j = 0; j < L; ++j) h[j] += valid ? (int32_t)(((m >> j) & 1u) << 1) - 1 : 0;
   } else {
-    const uint32_t m = mask_of<L>(words, x);
+    const uint32_t slot = ENC == kEncW8 ? (x & 0xFFFFFFu) : x;
+    const int32_t w = ENC == kEncW8 ? (int32_t)(int8_t)(x >> 24) : wv;
+    const uint32_t m = mask_of<L>(words, slot);
 #pragma unroll
-    for (int j = 0; j < L; ++j) h[j] += ((m >> j) & 1u) ? w8 : -w8;
+    for (int j = 0; j < L; ++j) h[j] += ((m >> j) & 1u) ? w : -w;
   }
 }
 
-// Local update (Eq. 2, J = -w, tie keeps) and the annealing flip.
+template <int L, int ENC, typename P>
+__device__ __forceinline__ void accumulate4(int32_t (&h)[L], const uint4 &x, uint32_t wv, P words) {
+  accumulate<L, ENC>(h, x.x, (int32_t)(int8_t)(wv), words);
+  accumulate<L, ENC>(h, x.y, (int32_t)(int8_t)(wv >> 8), words);
+  accumulate<L, ENC>(h, x.z, (int32_t)(int8_t)(wv >> 16), words);
+  accumulate<L, ENC>(h, x.w, (int32_t)(int8_t)(wv >> 24), words);
+}
+
+// Local update (Eq. 2 with J = -w, a zero field keeps the spin) and the
+// annealing flip of every replica bit.  The draw of replica r is word
+// (r mod 4) of the Philox block at counter {v, t, r div 4, 0}.
 template <int L>
-__device__ __forceinline__ uint32_t update_mask(const int32_t (&h)[L], uint32_t own, int32_t v,
-                                                uint32_t t, uint32_t T, const AnnealArgs &a) {
+__device__ __forceinline__ uint32_t update_mask(const int32_t (&h)[L], uint32_t own, int32_t v, uint32_t t,
+                                                uint32_t T, const AnnealArgs &a) {
   uint32_t nm = 0;
 #pragma unroll
   for (int j = 0; j < L; ++j) {
     uint32_t s = (own >> j) & 1u;
     s = h[j] > 0 ? 0u : (h[j] < 0 ? 1u : s);
-    if (T != 0u && (uint32_t)j < a.r_count) {
-      const uint32_t x = philox_w0((uint32_t)v, t, a.r0 + (uint32_t)j, 0u, a.seed_lo, a.seed_hi);
-      s ^= (x < T) ? 1u : 0u;
-    }
     nm |= s << j;
   }
-  return v >= 0 ? nm : 0u;
+  if (v < 0) return 0u;
+  if (T != 0u) {
+    const uint32_t live = a.r_count >= 32u ? 0xFFFFFFFFu : ((1u << a.r_count) - 1u);
+    uint32_t flips = 0;
+    if (L >= 4) {
+#pragma unroll
+      for (int jj = 0; jj < L / 4; ++jj) {
+        if ((uint32_t)(4 * jj) < a.r_count) {
+          const uint4 x = philox4((uint32_t)v, t, (a.r0 >> 2) + (uint32_t)jj, 0u, a.seed_lo, a.seed_hi);
+          const uint32_t f = (x.x < T ? 1u : 0u) | (x.y < T ? 2u : 0u) | (x.z < T ? 4u : 0u) | (x.w < T ? 8u : 0u);
+          flips |= f << (4 * jj);
+        }
+      }
+    } else {
+      const uint4 x = philox4((uint32_t)v, t, a.r0 >> 2, 0u, a.seed_lo, a.seed_hi);
+#pragma unroll
+      for (int j = 0; j < L; ++j) flips |= (word_of(x, (a.r0 + (uint32_t)j) & 3u) < T ? 1u : 0u) << j;
+    }
+    nm ^= flips & live;
+  }
+  return nm & lmask<L>();
 }
 
 template <typename T>
@@ -116,26 +151,45 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
-// Grid-wide barrier of a cooperative launch.  Returns false (and raises the
-// error flag) if the other workgroups did not arrive within the poll limit.
-__device__ bool grid_barrier(uint32_t *bar, uint32_t target, uint32_t limit) {
-  __shared__ uint32_t s_ok;
+// ---------------------------------------------------------------------------
+// Grid barrier of a cooperative launch: workgroups arrive on one of eight
+// group counters (blockIdx mod 8, i.e. one per XCD), the last arrival of a
+// group bumps the top counter, everybody polls the top counter.  Spin state
+// crosses workgroups only through agent-scope atomics, so with the LDS copy
+// a barrier needs no cache maintenance, only completed stores (s_waitcnt).
+// Without the LDS copy neighbour reads are plain loads and agent fences are
+// used.  A poll limit bounds the wait; hitting it raises the error flag and
+// every workgroup leaves the kernel.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void bar_arrive(uint32_t *bar, bool fenced) {
+  if (fenced)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  else
+    __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t ok = 1;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t polls = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-          ++polls > limit) {
-        __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t grp = blockIdx.x & 7u;
+    const uint32_t gsize = (gridDim.x - grp + 7u) / 8u;
+    const uint32_t old = __hip_atomic_fetch_add(bar + kBarGroup + 16 * grp, 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if ((old + 1u) % gsize == 0u)
+      __hip_atomic_fetch_add(bar + kBarTop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ bool bar_wait(uint32_t *bar, uint32_t target, uint32_t limit, bool fenced) {
+  __shared__ uint32_t s_ok;
+  if (threadIdx.x == 0) {
+    uint32_t ok = 1, polls = 0;
+    while (__hip_atomic_load(bar + kBarTop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(bar + kBarErr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++polls > limit) {
+        __hip_atomic_store(bar + kBarErr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();
@@ -145,144 +199,209 @@ __device__ bool grid_barrier(uint32_t *bar, uint32_t target, uint32_t limit) {
 // ---------------------------------------------------------------------------
 // Anneal kernel
 // ---------------------------------------------------------------------------
-template <int L, bool PM1, bool USE_LDS>
-__device__ __forceinline__ void run_slice(const AnnealArgs &a, const Item &it, uint32_t *lds,
-                                          int lane, uint32_t t, uint32_t T) {
-  const uint32_t slot = it.id * kSliceRows + lane;
-  const int32_t v = a.vid[slot];
+template <int L, int ENC>
+struct Fetched {
+  static constexpr int KM = kmax_for(L, ENC);
+  static constexpr int KW = ENC == kEncWide ? KM : 1;
+  uint4 e[KM];
+  uint32_t w[KW];  // separate weights (kEncWide only)
+  int32_t vid;
+  uint32_t ownw;   // the coherent spin word holding this lane's row
+};
+
+// Issues every load of one item: this lane's row id, its spin word and its
+// share of the sliced-ELL chunks (chunks g, g + G, ...).
+template <int L, int ENC>
+__device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it, int lane, Fetched<L, ENC> &f) {
+  constexpr int KM = Fetched<L, ENC>::KM;
+  const uint32_t G = it.g, K = 64u / G;
+  const uint32_t r = (uint32_t)lane / G, gl = (uint32_t)lane & (G - 1u);
+  const uint32_t slot = it.id + r;
+  f.vid = a.vid[slot];
+  f.ownw = ld_coherent(a.spins + ((slot * L) >> 5));
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    const uint32_t q = gl + (uint32_t)k * G;
+    if (q < it.len4) {
+      const size_t idx = (size_t)it.base4 + (size_t)q * K + r;
+      f.e[k] = a.entries[idx];
+      if (ENC == kEncWide) f.w[k < Fetched<L, ENC>::KW ? k : 0] = a.wts4[idx];
+    } else {
+      f.e[k] = ENC == kEncPm1 ? make_uint4(kSentinel, kSentinel, kSentinel, kSentinel) : make_uint4(0, 0, 0, 0);
+      if (ENC == kEncWide) f.w[k < Fetched<L, ENC>::KW ? k : 0] = 0u;
+    }
+  }
+}
+
+template <int L, int ENC, bool USE_LDS>
+__device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it, int lane, const Fetched<L, ENC> &f,
+                                        uint32_t *lds, uint32_t t, uint32_t T) {
+  constexpr int KM = Fetched<L, ENC>::KM;
+  const uint32_t G = it.g, K = 64u / G;
+  const uint32_t r = (uint32_t)lane / G, gl = (uint32_t)lane & (G - 1u);
+  const uint32_t slot = it.id + r;
   int32_t h[L];
 #pragma unroll
   for (int j = 0; j < L; ++j) h[j] = 0;
-  const uint4 *e = a.entries + it.base4 + lane;
-  const uint32_t *wq = PM1 ? nullptr : a.wts4 + it.base4 + lane;
-  const uint32_t len4 = it.len4;
-#pragma unroll 2
-  for (uint32_t q = 0; q < len4; ++q) {
-    const uint4 x = e[(size_t)q * kSliceRows];
-    const uint32_t wv = PM1 ? 0u : wq[(size_t)q * kSliceRows];
-    if (USE_LDS) {
-      accumulate<L, PM1>(h, x.x, (int32_t)(int8_t)(wv), lds);
-      accumulate<L, PM1>(h, x.y, (int32_t)(int8_t)(wv >> 8), lds);
-      accumulate<L, PM1>(h, x.z, (int32_t)(int8_t)(wv >> 16), lds);
-      accumulate<L, PM1>(h, x.w, (int32_t)(int8_t)(wv >> 24), lds);
-    } else {
-      accumulate<L, PM1>(h, x.x, (int32_t)(int8_t)(wv), a.spins);
-      accumulate<L, PM1>(h, x.y, (int32_t)(int8_t)(wv >> 8), a.spins);
-      accumulate<L, PM1>(h, x.z, (int32_t)(int8_t)(wv >> 16), a.spins);
-      accumulate<L, PM1>(h, x.w, (int32_t)(int8_t)(wv >> 24), a.spins);
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    if (gl + (uint32_t)k * G < it.len4) {
+      const uint32_t wv = ENC == kEncWide ? f.w[k < Fetched<L, ENC>::KW ? k : 0] : 0u;
+      if (USE_LDS)
+        accumulate4<L, ENC>(h, f.e[k], wv, lds);
+      else
+        accumulate4<L, ENC>(h, f.e[k], wv, a.spins);
     }
   }
-  const uint32_t own = USE_LDS ? mask_of<L>(lds, slot) : mask_of<L>(a.spins, slot);
-  const uint32_t nm = update_mask<L>(h, own, v, t, T, a);
-  // A slice's 64 masks fill 2L whole words.
-  if (L == 1) {
-    const unsigned long long b = __ballot(nm & 1u);
-    if (lane == 0) {
-      st_coherent64(reinterpret_cast<unsigned long long *>(a.spins) + it.id, b);
-      if (USE_LDS) reinterpret_cast<unsigned long long *>(lds)[it.id] = b;
+  // rows longer than the prefetch depth: the rest of the chunks
+  for (uint32_t q = gl + (uint32_t)KM * G; q < it.len4; q += G) {
+    const size_t idx = (size_t)it.base4 + (size_t)q * K + r;
+    const uint4 x = a.entries[idx];
+    const uint32_t wv = ENC == kEncWide ? a.wts4[idx] : 0u;
+    if (USE_LDS)
+      accumulate4<L, ENC>(h, x, wv, lds);
+    else
+      accumulate4<L, ENC>(h, x, wv, a.spins);
+  }
+  for (uint32_t off = 1; off < G; off <<= 1) {
+#pragma unroll
+    for (int j = 0; j < L; ++j) h[j] += __shfl_xor(h[j], (int)off);
+  }
+  const uint32_t bit0 = slot * L;
+  const uint32_t own = (f.ownw >> (bit0 & 31)) & lmask<L>();
+  const uint32_t nm = update_mask<L>(h, own, f.vid, t, T, a);
+  const bool rep = gl == 0u;
+  if (K * L >= 32u) {
+    // the item owns whole words: plain coherent stores
+    if (L == 1 && G == 1u) {
+      const unsigned long long b = __ballot(nm & 1u);
+      if (lane == 0) {
+        st_coherent64(reinterpret_cast<unsigned long long *>(a.spins) + (it.id >> 6), b);
+        if (USE_LDS) reinterpret_cast<unsigned long long *>(lds)[it.id >> 6] = b;
+      }
+    } else {
+      constexpr uint32_t P = 32u / L;  // rows per word
+      uint32_t val = rep ? nm << (bit0 & 31) : 0u;
+      for (uint32_t off = G; off < G * P; off <<= 1) val |= __shfl_xor(val, (int)off);
+      if (rep && (r % P) == 0u) {
+        st_coherent(a.spins + (bit0 >> 5), val);
+        if (USE_LDS) lds[bit0 >> 5] = val;
+      }
     }
   } else {
-    constexpr int P = 32 / L;  // slots per word
-    uint32_t val = nm << ((lane % P) * L);
-#pragma unroll
-    for (int off = 1; off < P; off <<= 1) val |= __shfl_xor(val, off);
-    if (lane % P == 0) {
-      const uint32_t word = it.id * (2 * L) + lane / P;
-      st_coherent(a.spins + word, val);
-      if (USE_LDS) lds[word] = val;
+    // all K rows share one word with other items: exact XOR of the changes
+    uint32_t chg = rep ? (own ^ nm) << (bit0 & 31) : 0u;
+    for (uint32_t off = G; off < 64u; off <<= 1) chg |= __shfl_xor(chg, (int)off);
+    if (lane == 0 && chg != 0u) {
+      __hip_atomic_fetch_xor(a.spins + (bit0 >> 5), chg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (USE_LDS) atomicXor(lds + (bit0 >> 5), chg);
     }
   }
 }
 
-template <int L, bool PM1, bool USE_LDS>
-__device__ __forceinline__ void run_long(const AnnealArgs &a, const Item &it, uint32_t *lds,
-                                         int lane, uint32_t t, uint32_t T) {
-  const uint32_t slot = it.id;
-  const int32_t v = a.vid[slot];
-  int32_t h[L];
-#pragma unroll
-  for (int j = 0; j < L; ++j) h[j] = 0;
-  for (uint32_t q = lane; q < it.len4; q += kWave) {
-    const uint4 x = a.entries[(size_t)it.base4 + q];
-    const uint32_t wv = PM1 ? 0u : a.wts4[(size_t)it.base4 + q];
-    if (USE_LDS) {
-      accumulate<L, PM1>(h, x.x, (int32_t)(int8_t)(wv), lds);
-      accumulate<L, PM1>(h, x.y, (int32_t)(int8_t)(wv >> 8), lds);
-      accumulate<L, PM1>(h, x.z, (int32_t)(int8_t)(wv >> 16), lds);
-      accumulate<L, PM1>(h, x.w, (int32_t)(int8_t)(wv >> 24), lds);
-    } else {
-      accumulate<L, PM1>(h, x.x, (int32_t)(int8_t)(wv), a.spins);
-      accumulate<L, PM1>(h, x.y, (int32_t)(int8_t)(wv >> 8), a.spins);
-      accumulate<L, PM1>(h, x.z, (int32_t)(int8_t)(wv >> 16), a.spins);
-      accumulate<L, PM1>(h, x.w, (int32_t)(int8_t)(wv >> 24), a.spins);
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < L; ++j) h[j] = wave_sum(h[j]);
-  if (lane == 0) {
-    const uint32_t own = USE_LDS ? mask_of<L>(lds, slot) : mask_of<L>(a.spins, slot);
-    const uint32_t nm = update_mask<L>(h, own, v, t, T, a);
-    const uint32_t bit = slot * L;
-    const uint32_t change = (own ^ nm) << (bit & 31);
-    if (change != 0u) {
-      __hip_atomic_fetch_xor(a.spins + (bit >> 5), change, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (USE_LDS) atomicXor(lds + (bit >> 5), change);
-    }
-  }
+// Copies spin words [b, e) (64-bit units) from the coherent global state into
+// LDS; the calling threads split the range as (first, stride).
+__device__ __forceinline__ void restage(const AnnealArgs &a, uint32_t *lds, uint32_t b, uint32_t e,
+                                        uint32_t first, uint32_t stride) {
+  const unsigned long long *g64 = reinterpret_cast<const unsigned long long *>(a.spins);
+  unsigned long long *l64 = reinterpret_cast<unsigned long long *>(lds);
+  for (uint32_t i = b + first; i < e; i += stride) l64[i] = ld_coherent64(g64 + i);
 }
 
-template <int L, bool PM1, bool USE_LDS>
+template <int L, int ENC, bool USE_LDS>
 __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   extern __shared__ uint32_t lds[];
+  constexpr int kWaves = kAnnealBlock / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  const int gw = blockIdx.x * (kAnnealBlock / kWave) + (threadIdx.x / kWave);
+  const int wib = threadIdx.x / kWave;
+  const int gw = blockIdx.x * kWaves + wib;
   const bool multi = gridDim.x > 1;
+  const bool fenced = !USE_LDS;
+  const uint32_t n_grp = gridDim.x < 8u ? gridDim.x : 8u;
   if (USE_LDS) {
-    const unsigned long long *g64 = reinterpret_cast<const unsigned long long *>(a.spins);
-    unsigned long long *l64 = reinterpret_cast<unsigned long long *>(lds);
-    for (uint32_t i = threadIdx.x; i < a.n_words / 2; i += blockDim.x) l64[i] = ld_coherent64(g64 + i);
+    restage(a, lds, 0, a.n_words / 2, threadIdx.x, blockDim.x);
     __syncthreads();
   }
-  uint32_t target = 0;
+  if (a.n_phases <= 0 || a.t_begin >= a.t_end) return;
+  uint32_t epoch = 0;
+  const size_t stride = (size_t)a.nw + 1;
+  uint32_t ib = a.wave_ptr[gw], ie = a.wave_ptr[gw + 1];
+  Fetched<L, ENC> fa, fb;
+  Item ita;
+  if (ib < ie) {
+    ita = a.items[ib];
+    fetch<L, ENC>(a, ita, lane, fa);
+  }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
     const uint32_t T = a.thr[t];
     for (int32_t ph = 0; ph < a.n_phases; ++ph) {
-      const uint32_t *wp = a.wave_ptr + (size_t)ph * (a.nw + 1) + gw;
-      const uint32_t ib = wp[0], ie = wp[1];
+      // items of this phase, one ahead in flight
       for (uint32_t i = ib; i < ie; ++i) {
-        const Item it = a.items[i];
-        if (it.kind == kItemSlice)
-          run_slice<L, PM1, USE_LDS>(a, it, lds, lane, (uint32_t)t, T);
-        else
-          run_long<L, PM1, USE_LDS>(a, it, lds, lane, (uint32_t)t, T);
+        const bool more = i + 1 < ie;
+        Item itb;
+        if (more) {
+          itb = a.items[i + 1];
+          fetch<L, ENC>(a, itb, lane, fb);
+        }
+        compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, T);
+        if (more) {
+          ita = itb;
+          fa = fb;
+        }
       }
-      if (multi) {
-        if (!a.async_mode) {
-          target += gridDim.x;
-          if (!grid_barrier(a.bar, target, a.spin_limit)) return;
-        } else {
+      // the next phase's item range and first item
+      const bool last_phase = ph + 1 == a.n_phases;
+      const int32_t nph = last_phase ? 0 : ph + 1;
+      const bool done = last_phase && t + 1 == a.t_end;
+      ib = a.wave_ptr[(size_t)nph * stride + gw];
+      ie = a.wave_ptr[(size_t)nph * stride + gw + 1];
+      if (done) ie = ib;
+      if (multi && !a.async_mode) {
+        // deterministic: barrier, then refresh the class just written
+        bar_arrive(a.bar, fenced);
+        if (ib < ie) {
+          ita = a.items[ib];
+          fetch<L, ENC>(a, ita, lane, fa);
+        }
+        ++epoch;
+        if (!bar_wait(a.bar, epoch * n_grp, a.spin_limit, fenced)) return;
+        if (USE_LDS) {
+          restage(a, lds, a.cls_w64[ph], a.cls_w64[ph + 1], threadIdx.x, blockDim.x);
           __syncthreads();
         }
+      } else if (multi) {
+        // async: no grid-wide wait inside a sweep.  The workgroup drains its
+        // stores and meets, so no refresh can overwrite a fresher LDS word
+        // of its own, then each wave refreshes its share of the phase's
+        // classes from the global state and moves on.
         if (USE_LDS) {
-          // refresh this class's spins from the coherent global state
-          const unsigned long long *g64 = reinterpret_cast<const unsigned long long *>(a.spins);
-          unsigned long long *l64 = reinterpret_cast<unsigned long long *>(lds);
-          const uint32_t b = a.cls_w64[ph], e = a.cls_w64[ph + 1];
-          for (uint32_t i = b + threadIdx.x; i < e; i += blockDim.x) l64[i] = ld_coherent64(g64 + i);
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
         }
-        __syncthreads();
+        if (ib < ie) {
+          ita = a.items[ib];
+          fetch<L, ENC>(a, ita, lane, fa);
+        }
+        if (USE_LDS)
+          restage(a, lds, a.cls_w64[ph], a.cls_w64[ph + 1], (uint32_t)(wib * kWave + lane), blockDim.x);
+        if (last_phase && !done) {
+          // sweeps stay synchronised
+          bar_arrive(a.bar, fenced);
+          ++epoch;
+          if (!bar_wait(a.bar, epoch * n_grp, a.spin_limit, fenced)) return;
+        }
       } else {
-        // one workgroup: its LDS copy is current; without one, make this
-        // phase's global writes visible to the next phase's plain loads
-        if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // one workgroup: its LDS copy is current
+        if (ib < ie) {
+          ita = a.items[ib];
+          fetch<L, ENC>(a, ita, lane, fa);
+        }
+        if (!a.async_mode || last_phase) {
+          if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __syncthreads();
+          if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
       }
-    }
-    if (multi && a.async_mode) {
-      // sweeps stay synchronised: nobody starts sweep t+1 before all finished t
-      target += gridDim.x;
-      if (!grid_barrier(a.bar, target, a.spin_limit)) return;
     }
   }
 }
@@ -300,8 +419,9 @@ __global__ void k_randomize(uint32_t *spins, const int32_t *vid, uint32_t n_word
       const int32_t v = vid[wi * P + i];
       if (v < 0) continue;
       for (uint32_t j = 0; j < (uint32_t)L && j < r_count; ++j) {
-        const uint32_t x = philox_w0((uint32_t)v, 0u, r0 + j, 1u, k0, k1);
-        word |= (x >> 31) << (i * L + j);
+        const uint32_t r = r0 + j;
+        const uint4 x = philox4((uint32_t)v, 0u, r >> 2, 1u, k0, k1);
+        word |= (word_of(x, r & 3u) >> 31) << (i * L + j);
       }
     }
     spins[wi] = word;
@@ -359,7 +479,7 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t count, uint32_t value) {
 // Cut and energy (Eq. 4 and Eq. 5 with J = -w) of one replica bit, summed
 // over directed entries (each undirected edge twice).
 // ---------------------------------------------------------------------------
-template <int L, bool PM1>
+template <int L, int ENC>
 __global__ __launch_bounds__(256) void k_cut(CutArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -367,26 +487,28 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs a) {
   long long e_sum = 0, c_sum = 0;
   for (uint32_t i = wave; i < a.n_items; i += n_waves) {
     const Item it = a.items[i];
-    const bool slice = it.kind == kItemSlice;
-    const uint32_t slot = slice ? it.id * kSliceRows + lane : it.id;
+    const uint32_t G = it.g, K = 64u / G;
+    const uint32_t r = (uint32_t)lane / G, gl = (uint32_t)lane & (G - 1u);
+    const uint32_t slot = it.id + r;
     const uint32_t own = (mask_of<L>(a.spins, slot) >> a.bit) & 1u;
     int32_t e_part = 0, c_part = 0;
-    const uint32_t q0 = slice ? 0u : (uint32_t)lane;
-    const uint32_t qs = slice ? 1u : (uint32_t)kWave;
-    for (uint32_t q = q0; q < it.len4; q += qs) {
-      const size_t c = slice ? (size_t)it.base4 + (size_t)q * kSliceRows + lane : (size_t)it.base4 + q;
+    for (uint32_t q = gl; q < it.len4; q += G) {
+      const size_t c = (size_t)it.base4 + (size_t)q * K + r;
       const uint4 x4 = a.entries[c];
-      const uint32_t wv = PM1 ? 0u : a.wts4[c];
+      const uint32_t wv = ENC == kEncWide ? a.wts4[c] : 0u;
       const uint32_t xs[4] = {x4.x, x4.y, x4.z, x4.w};
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const uint32_t x = xs[k];
         int32_t w;
         uint32_t nb;
-        if (PM1) {
+        if (ENC == kEncPm1) {
           if (x == kSentinel) continue;
           w = (x & kSignBit) ? -1 : 1;
           nb = x & ~kSignBit;
+        } else if (ENC == kEncW8) {
+          w = (int32_t)(int8_t)(x >> 24);
+          nb = x & 0xFFFFFFu;
         } else {
           w = (int32_t)(int8_t)(wv >> (8 * k));
           nb = x;
@@ -419,9 +541,9 @@ hipError_t set_lds_limit(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int L, bool PM1, bool USE_LDS>
+template <int L, int ENC, bool USE_LDS>
 hipError_t launch_anneal_t(const AnnealArgs &a, int grid, size_t lds_bytes, hipStream_t s) {
-  auto kern = k_anneal<L, PM1, USE_LDS>;
+  auto kern = k_anneal<L, ENC, USE_LDS>;
   if (USE_LDS) {
     hipError_t e = set_lds_limit(kern, lds_bytes);
     if (e != hipSuccess) return e;
@@ -432,9 +554,9 @@ hipError_t launch_anneal_t(const AnnealArgs &a, int grid, size_t lds_bytes, hipS
                                     args, USE_LDS ? (unsigned)lds_bytes : 0u, s);
 }
 
-template <int L, bool PM1, bool USE_LDS>
+template <int L, int ENC, bool USE_LDS>
 hipError_t occupancy_t(int *blocks, size_t lds_bytes) {
-  auto kern = k_anneal<L, PM1, USE_LDS>;
+  auto kern = k_anneal<L, ENC, USE_LDS>;
   if (USE_LDS) {
     hipError_t e = set_lds_limit(kern, lds_bytes);
     if (e != hipSuccess) return e;
@@ -457,15 +579,25 @@ hipError_t occupancy_t(int *blocks, size_t lds_bytes) {
   }
 
 namespace {
-template <int L>
-hipError_t anneal_L(const AnnealArgs &a, bool pm1, bool use_lds, int grid, size_t lds, hipStream_t s) {
-  if (pm1) return use_lds ? launch_anneal_t<L, true, true>(a, grid, lds, s) : launch_anneal_t<L, true, false>(a, grid, lds, s);
-  return use_lds ? launch_anneal_t<L, false, true>(a, grid, lds, s) : launch_anneal_t<L, false, false>(a, grid, lds, s);
+template <int L, int ENC>
+hipError_t anneal_LE(const AnnealArgs &a, bool use_lds, int grid, size_t lds, hipStream_t s) {
+  return use_lds ? launch_anneal_t<L, ENC, true>(a, grid, lds, s) : launch_anneal_t<L, ENC, false>(a, grid, lds, s);
 }
 template <int L>
-hipError_t occ_L(bool pm1, bool use_lds, size_t lds, int *blocks) {
-  if (pm1) return use_lds ? occupancy_t<L, true, true>(blocks, lds) : occupancy_t<L, true, false>(blocks, lds);
-  return use_lds ? occupancy_t<L, false, true>(blocks, lds) : occupancy_t<L, false, false>(blocks, lds);
+hipError_t anneal_L(const AnnealArgs &a, int enc, bool use_lds, int grid, size_t lds, hipStream_t s) {
+  if (enc == kEncPm1) return anneal_LE<L, kEncPm1>(a, use_lds, grid, lds, s);
+  if (enc == kEncW8) return anneal_LE<L, kEncW8>(a, use_lds, grid, lds, s);
+  return anneal_LE<L, kEncWide>(a, use_lds, grid, lds, s);
+}
+template <int L, int ENC>
+hipError_t occ_LE(bool use_lds, size_t lds, int *blocks) {
+  return use_lds ? occupancy_t<L, ENC, true>(blocks, lds) : occupancy_t<L, ENC, false>(blocks, lds);
+}
+template <int L>
+hipError_t occ_L(int enc, bool use_lds, size_t lds, int *blocks) {
+  if (enc == kEncPm1) return occ_LE<L, kEncPm1>(use_lds, lds, blocks);
+  if (enc == kEncW8) return occ_LE<L, kEncW8>(use_lds, lds, blocks);
+  return occ_LE<L, kEncWide>(use_lds, lds, blocks);
 }
 template <int L>
 hipError_t randomize_L(uint32_t *spins, const int32_t *vid, uint32_t n_words, uint32_t r0, uint32_t rc,
@@ -490,23 +622,25 @@ hipError_t get_L(const uint32_t *spins, const int32_t *vid, uint32_t n_slots, in
   return hipGetLastError();
 }
 template <int L>
-hipError_t cut_L(const CutArgs &a, bool pm1, hipStream_t s) {
+hipError_t cut_L(const CutArgs &a, int enc, hipStream_t s) {
   const int grid = (int)std::min<uint32_t>(2048u, a.n_items / 4 + 1);
-  if (pm1)
-    hipLaunchKernelGGL((k_cut<L, true>), dim3(grid), dim3(256), 0, s, a);
+  if (enc == kEncPm1)
+    hipLaunchKernelGGL((k_cut<L, kEncPm1>), dim3(grid), dim3(256), 0, s, a);
+  else if (enc == kEncW8)
+    hipLaunchKernelGGL((k_cut<L, kEncW8>), dim3(grid), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_cut<L, false>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_cut<L, kEncWide>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_anneal(int L, bool pm1, bool use_lds, const AnnealArgs &a, int grid, size_t lds_bytes,
+hipError_t launch_anneal(int L, int enc, bool use_lds, const AnnealArgs &a, int grid, size_t lds_bytes,
                          hipStream_t s) {
-  ISING_DISPATCH_L(L, anneal_L, a, pm1, use_lds, grid, lds_bytes, s);
+  ISING_DISPATCH_L(L, anneal_L, a, enc, use_lds, grid, lds_bytes, s);
 }
 
-hipError_t anneal_occupancy(int L, bool pm1, bool use_lds, size_t lds_bytes, int *blocks_per_cu) {
-  ISING_DISPATCH_L(L, occ_L, pm1, use_lds, lds_bytes, blocks_per_cu);
+hipError_t anneal_occupancy(int L, int enc, bool use_lds, size_t lds_bytes, int *blocks_per_cu) {
+  ISING_DISPATCH_L(L, occ_L, enc, use_lds, lds_bytes, blocks_per_cu);
 }
 
 hipError_t launch_randomize(int L, uint32_t *spins, const int32_t *vid, uint32_t n_words, uint32_t r0,
@@ -524,8 +658,8 @@ hipError_t launch_get_spins(int L, const uint32_t *spins, const int32_t *vid, ui
   ISING_DISPATCH_L(L, get_L, spins, vid, n_slots, dst, n, r0, r_count, s);
 }
 
-hipError_t launch_cut(int L, bool pm1, const CutArgs &a, hipStream_t s) {
-  ISING_DISPATCH_L(L, cut_L, a, pm1, s);
+hipError_t launch_cut(int L, int enc, const CutArgs &a, hipStream_t s) {
+  ISING_DISPATCH_L(L, cut_L, a, enc, s);
 }
 
 hipError_t launch_check_spins(const int8_t *src, int64_t count, uint32_t *flag, hipStream_t s) {

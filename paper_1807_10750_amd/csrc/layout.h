@@ -3,22 +3,23 @@
 // Vertices are renumbered into "slots": colour class by colour class (the
 // classes of the greedy colouring that orders the deterministic sweep), each
 // class padded to a multiple of 64 slots, and inside a class by decreasing
-// degree.  Rows are grouped into slices of 64 consecutive slots, one per
-// 64-lane wavefront:
-//   * a short slice (max degree <= long threshold) is one work item processed
-//     lane-per-row from a sliced-ELL edge block: entry q of row i of the
-//     slice lives at uint4 chunk (q / 4) * 64 + i, component q % 4, so each
-//     wavefront load reads 1 KiB of contiguous memory;
-//   * rows of a long slice are one work item each, processed by a whole
-//     wavefront that strides the row's contiguous, 4-padded entry list.
-// An edge entry is a uint32: the neighbour's slot, and for graphs whose
-// weights are all +-1 the weight's sign in bit 31 (padding = kSentinel).
-// Other graphs keep slot-only entries plus one int8 weight per entry
-// (padding = slot 0 with weight 0).
+// degree.  A work item is one wavefront's worth of rows: K = 64 / G
+// consecutive slots, G lanes per row, G in {1, 4, 16, 64} chosen from the
+// row degree.  Items start at multiples of K.  The item's edge entries form a
+// sliced-ELL block: every row is padded to len4 chunks of 4 entries and chunk
+// q of row r sits at uint4 index base4 + q * K + r, so lane (r, g) reads
+// chunks g, g + G, g + 2G, ... and every wavefront load covers 1 KiB of
+// contiguous memory.
+// An edge entry is a uint32 in one of three encodings:
+//   kEncPm1  (every weight +-1): slot | sign << 31, padding = kSentinel;
+//   kEncW8   (fewer than 2^24 slots): slot | weight << 24, padding = 0;
+//   kEncWide (otherwise): slot only, plus one int8 weight per entry in a
+//            separate stream, padding = slot 0 with weight 0.
 //
 // Spins live as an L-bit mask per slot (bit j = replica j of the group,
 // 1 = +1), L in {1,2,4,8,16,32}; the masks of 32/L consecutive slots share
-// one uint32 word, so the state of n slots is n*L/32 words.
+// one uint32 word, so the state of n slots is n*L/32 words.  An item with
+// K * L >= 32 owns whole words; smaller items share one word with others.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -27,17 +28,26 @@ namespace ising {
 
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 constexpr uint32_t kSignBit = 0x80000000u;
-constexpr int kSliceRows = 64;
 
-enum ItemKind : uint32_t { kItemSlice = 0, kItemLong = 1 };
+// Chunks of 4 entries each lane prefetches per item; bounds the degree of a
+// row handled with G lanes to 4 * kmax * G (longer rows loop).
+enum Encoding { kEncPm1 = 0, kEncW8 = 1, kEncWide = 2 };
+constexpr int kmax_for(int L, int enc) { return (L >= 32 || enc == kEncWide || (enc == kEncW8 && L >= 2)) ? 2 : 4; }
 
 // One unit of work for one wavefront.
 struct Item {
-  uint32_t id;     // slice: slice index (slots 64*id .. 64*id+63); long: slot of the row
+  uint32_t id;     // first slot (a multiple of K = 64 / g)
   uint32_t base4;  // index of the item's first uint4 chunk in the entry stream
-  uint32_t len4;   // slice: chunks per lane; long: chunks in the row
-  uint32_t kind;   // ItemKind
+  uint32_t len4;   // chunks per row
+  uint32_t g;      // lanes per row: 1, 4, 16 or 64
 };
+
+// Words of the per-handle flag buffer.
+constexpr int kBarTop = 0;       // barrier epochs completed x groups
+constexpr int kBarErr = 1;       // set when a barrier poll limit is hit
+constexpr int kBarCheck = 2;     // spin-value check result
+constexpr int kBarGroup = 16;    // group counter k at kBarGroup + 16 * k, k < 8
+constexpr int kBarWords = 256;
 
 // Arguments of the anneal kernel (passed by value).
 struct AnnealArgs {
@@ -49,7 +59,7 @@ struct AnnealArgs {
   const uint32_t *cls_w64;   // [n_phases + 1] class boundaries in 64-bit words of the spin state
   uint32_t *spins;           // this replica group's spin words
   const uint32_t *thr;       // thresholds, indexed by absolute sweep
-  uint32_t *bar;             // [0] barrier counter, [1] error flag
+  uint32_t *bar;             // barrier words (see kBar*), error flag
   uint32_t n_words;          // spin words of the group
   int32_t n_phases;
   int32_t nw;                // wavefronts in the grid

@@ -129,15 +129,21 @@ int32_t greedy_coloring(const HostCSR &g, bool largest_first, std::vector<int32_
   return n_colors;
 }
 
-int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors,
-                 int64_t long_deg, HostLayout *out, std::string *msg) {
+int choose_encoding(const HostCSR &g, int64_t n_slots) {
+  bool pm1 = true;
+  for (int64_t k = 0; k < g.nnz; ++k)
+    if (g.w[k] != 1 && g.w[k] != -1) { pm1 = false; break; }
+  if (pm1) return kEncPm1;
+  return n_slots <= ((int64_t)1 << 24) ? kEncW8 : kEncWide;
+}
+
+int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors, int enc, int kmax,
+                 int bin_shift, HostLayout *out, std::string *msg) {
   HostLayout &L = *out;
   const int64_t n = g.n;
   const int64_t *rp = g.row_ptr;
   try {
-    L.pm1 = true;
-    for (int64_t k = 0; k < g.nnz; ++k)
-      if (g.w[k] != 1 && g.w[k] != -1) { L.pm1 = false; break; }
+    L.enc = enc;
     L.n_phases = n_colors;
     // vertices of each class, by (degree desc, id asc)
     std::vector<int64_t> cnt(n_colors + 1, 0);
@@ -156,7 +162,7 @@ int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_
     L.cls_begin.assign(n_colors + 1, 0);
     for (int32_t c = 0; c < n_colors; ++c) {
       const int64_t size = cnt[c + 1] - cnt[c];
-      L.cls_begin[c + 1] = L.cls_begin[c] + (size + kSliceRows - 1) / kSliceRows * kSliceRows;
+      L.cls_begin[c + 1] = L.cls_begin[c] + (size + 63) / 64 * 64;
     }
     L.n_slots = L.cls_begin[n_colors];
     if (L.n_slots >= (int64_t)0x7FFFFFFF) { *msg = "too many vertices"; return kPrepArg; }
@@ -168,57 +174,56 @@ int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_
         L.vid[slot] = byc[i];
         L.slot_of[byc[i]] = (int32_t)slot;
       }
-    // items and entry offsets
+    // Items: walk each class's rows (degree descending).  An item starting
+    // at class position pos takes G lanes per row, the smallest G in
+    // {1, 4, 16, 64} whose prefetch depth covers the first (largest) row's
+    // degree, widened until K = 64 / G divides pos; it spans K rows.
     L.items.clear();
     L.phase_items.assign(n_colors + 1, 0);
     uint64_t chunks = 0;  // uint4 chunks allocated so far
+    auto lanes_for = [&](int64_t d) -> uint32_t {
+      for (uint32_t lanes = 1; lanes < 64; lanes *= 4)
+        if (d <= ((4 * (int64_t)kmax * (int64_t)lanes) >> bin_shift)) return lanes;
+      return 64;
+    };
     for (int32_t c = 0; c < n_colors; ++c) {
-      for (int64_t s0 = L.cls_begin[c]; s0 < L.cls_begin[c + 1]; s0 += kSliceRows) {
-        const int32_t first = L.vid[s0];
-        const int64_t dmax = first >= 0 ? deg(first) : 0;
-        if (dmax > long_deg) {
-          for (int64_t r = s0; r < s0 + kSliceRows; ++r) {
-            if (L.vid[r] < 0) continue;
-            const uint64_t len4 = (uint64_t)(deg(L.vid[r]) + 3) / 4;
-            L.items.push_back(Item{(uint32_t)r, (uint32_t)chunks, (uint32_t)len4, kItemLong});
-            L.max_long_len4 = std::max<int64_t>(L.max_long_len4, (int64_t)len4);
-            chunks += len4;
-          }
-        } else {
-          const uint64_t len4 = (uint64_t)(dmax + 3) / 4;
-          L.items.push_back(Item{(uint32_t)(s0 / kSliceRows), (uint32_t)chunks, (uint32_t)len4, kItemSlice});
-          chunks += len4 * kSliceRows;
-        }
+      const int64_t size = cnt[c + 1] - cnt[c];
+      for (int64_t pos = 0; pos < size;) {
+        const int32_t first = L.vid[L.cls_begin[c] + pos];
+        const int64_t dmax = deg(first);
+        uint32_t lanes = lanes_for(dmax);
+        while (pos % (64 / lanes) != 0) lanes *= 4;
+        const uint32_t K = 64 / lanes;
+        const uint64_t len4 = (uint64_t)(dmax + 3) / 4;
+        L.items.push_back(Item{(uint32_t)(L.cls_begin[c] + pos), (uint32_t)chunks, (uint32_t)len4, lanes});
+        chunks += len4 * K;
+        pos += K;
         if (chunks >= (uint64_t)0xFFFFFFFFu) { *msg = "edge stream too large"; return kPrepArg; }
       }
       L.phase_items[c + 1] = (uint32_t)L.items.size();
     }
     // fill the entry stream
-    const uint32_t pad = L.pm1 ? kSentinel : 0u;
+    const uint32_t pad = L.enc == kEncPm1 ? kSentinel : 0u;
     L.entries.assign(chunks * 4, pad);
-    if (!L.pm1) L.wts.assign(chunks * 4, 0);
-    auto put = [&](uint64_t pos, int64_t k) {
-      const uint32_t slot = (uint32_t)L.slot_of[g.col[k]];
-      if (L.pm1) {
-        L.entries[pos] = slot | (g.w[k] < 0 ? kSignBit : 0u);
-      } else {
-        L.entries[pos] = slot;
-        L.wts[pos] = g.w[k];
-      }
-    };
+    if (L.enc == kEncWide) L.wts.assign(chunks * 4, 0);
     for (const Item &it : L.items) {
-      if (it.kind == kItemLong) {
-        const int32_t v = L.vid[it.id];
-        uint64_t pos = (uint64_t)it.base4 * 4;
-        for (int64_t k = rp[v]; k < rp[v + 1]; ++k) put(pos++, k);
-      } else {
-        for (int lane = 0; lane < kSliceRows; ++lane) {
-          const int32_t v = L.vid[(int64_t)it.id * kSliceRows + lane];
-          if (v < 0) continue;
-          int64_t q = 0;
-          for (int64_t k = rp[v]; k < rp[v + 1]; ++k, ++q) {
-            const uint64_t chunk = (uint64_t)it.base4 + (uint64_t)(q / 4) * kSliceRows + lane;
-            put(chunk * 4 + (q % 4), k);
+      const uint32_t K = 64 / it.g;
+      for (uint32_t r = 0; r < K; ++r) {
+        const int64_t slot = (int64_t)it.id + r;
+        if (slot >= L.n_slots) break;
+        const int32_t v = L.vid[slot];
+        if (v < 0) continue;
+        int64_t q = 0;
+        for (int64_t k = rp[v]; k < rp[v + 1]; ++k, ++q) {
+          const uint64_t pos = ((uint64_t)it.base4 + (uint64_t)(q / 4) * K + r) * 4 + (q % 4);
+          const uint32_t nb = (uint32_t)L.slot_of[g.col[k]];
+          if (L.enc == kEncPm1) {
+            L.entries[pos] = nb | (g.w[k] < 0 ? kSignBit : 0u);
+          } else if (L.enc == kEncW8) {
+            L.entries[pos] = nb | ((uint32_t)(uint8_t)g.w[k] << 24);
+          } else {
+            L.entries[pos] = nb;
+            L.wts[pos] = g.w[k];
           }
         }
       }
@@ -230,14 +235,38 @@ int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_
   return kPrepOk;
 }
 
-std::vector<uint32_t> partition_waves(const HostLayout &L, int32_t nw) {
-  std::vector<uint32_t> out((size_t)L.n_phases * (nw + 1));
-  for (int32_t p = 0; p < L.n_phases; ++p) {
-    const uint32_t b = L.phase_items[p], e = L.phase_items[p + 1];
+std::vector<int32_t> phase_classes(const HostLayout &L, const std::vector<int64_t> &class_size, int merge_div) {
+  std::vector<int32_t> out{0};
+  int64_t total = 0;
+  for (int64_t c : class_size) total += c;
+  const int64_t big = merge_div > 0 ? (total + merge_div - 1) / merge_div : 0;
+  int64_t run = 0;
+  for (int32_t c = 0; c < L.n_phases; ++c) {
+    if (merge_div <= 0 || class_size[c] >= big) {
+      if (run > 0) out.push_back(c);  // close the pending run of small classes
+      out.push_back(c + 1);
+      run = 0;
+      continue;
+    }
+    run += class_size[c];
+    if (run >= big) {
+      out.push_back(c + 1);
+      run = 0;
+    }
+  }
+  if (out.back() != L.n_phases) out.push_back(L.n_phases);
+  return out;
+}
+
+std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int32_t> &phase_cls, int32_t nw) {
+  const int32_t n_ph = (int32_t)phase_cls.size() - 1;
+  std::vector<uint32_t> out((size_t)n_ph * (nw + 1));
+  for (int32_t p = 0; p < n_ph; ++p) {
+    const uint32_t b = L.phase_items[phase_cls[p]], e = L.phase_items[phase_cls[p + 1]];
     std::vector<uint64_t> prefix(e - b + 1, 0);
     for (uint32_t i = b; i < e; ++i) {
       const Item &it = L.items[i];
-      const uint64_t cost = 64 + (uint64_t)it.len4 * (it.kind == kItemSlice ? 4 * kSliceRows : 4);
+      const uint64_t cost = 64 + (uint64_t)it.len4 * 4 * (64 / it.g);
       prefix[i - b + 1] = prefix[i - b] + cost;
     }
     const uint64_t total = prefix.back();
@@ -258,13 +287,10 @@ bool check_layout(const HostLayout &L, std::string *msg) {
   const uint64_t chunks = L.entries.size() / 4;
   for (size_t i = 0; i < L.items.size(); ++i) {
     const Item &it = L.items[i];
-    bool ok;
-    if (it.kind == kItemSlice)
-      ok = ((int64_t)it.id + 1) * kSliceRows <= L.n_slots &&
-           (uint64_t)it.base4 + (uint64_t)it.len4 * kSliceRows <= chunks;
-    else
-      ok = (int64_t)it.id < L.n_slots && (uint64_t)it.base4 + it.len4 <= chunks &&
-           L.vid[it.id] >= 0;
+    const bool g_ok = it.g == 1 || it.g == 4 || it.g == 16 || it.g == 64;
+    const uint32_t K = g_ok ? 64 / it.g : 1;
+    const bool ok = g_ok && it.id % K == 0 && (int64_t)it.id + K <= L.n_slots &&
+                    (uint64_t)it.base4 + (uint64_t)it.len4 * K <= chunks && L.vid[it.id] >= 0;
     if (!ok) {
       *msg = "layout item " + std::to_string(i) + " out of range";
       return false;
@@ -272,15 +298,15 @@ bool check_layout(const HostLayout &L, std::string *msg) {
   }
   for (size_t k = 0; k < L.entries.size(); ++k) {
     const uint32_t x = L.entries[k];
-    if (L.pm1 && x == kSentinel) continue;
-    const uint32_t slot = L.pm1 ? (x & ~kSignBit) : x;
+    if (L.enc == kEncPm1 && x == kSentinel) continue;
+    const uint32_t slot = L.enc == kEncPm1 ? (x & ~kSignBit) : (L.enc == kEncW8 ? (x & 0xFFFFFFu) : x);
     if ((int64_t)slot >= L.n_slots || L.vid[slot] < 0) {
       *msg = "layout entry " + std::to_string(k) + " names a bad slot";
       return false;
     }
   }
   for (int32_t p = 0; p < L.n_phases; ++p)
-    if (L.cls_begin[p] % kSliceRows != 0 || L.phase_items[p] > L.phase_items[p + 1]) {
+    if (L.cls_begin[p] % 64 != 0 || L.phase_items[p] > L.phase_items[p + 1]) {
       *msg = "layout class table inconsistent";
       return false;
     }

@@ -42,7 +42,7 @@ int32_t greedy_coloring(const HostCSR &g, bool largest_first, std::vector<int32_
 struct HostLayout {
   int64_t n_slots = 0;                 // multiple of 64
   int32_t n_phases = 0;                // colour classes
-  bool pm1 = false;                    // every weight is +1 or -1
+  int enc = 0;                         // Encoding of the entries
   std::vector<int32_t> vid;            // slot -> vertex (-1 = padding)
   std::vector<int32_t> slot_of;        // vertex -> slot
   std::vector<int64_t> cls_begin;      // [n_phases + 1] first slot of each class
@@ -50,17 +50,26 @@ struct HostLayout {
   std::vector<int8_t> wts;             // per entry (general weights only)
   std::vector<Item> items;             // phase by phase
   std::vector<uint32_t> phase_items;   // [n_phases + 1]
-  int64_t max_long_len4 = 0;
 };
 
-// long_deg: rows of a slice whose largest degree exceeds it become
-// wavefront-per-row items.
-int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors,
-                 int64_t long_deg, HostLayout *out, std::string *msg);
+// The entry encoding a graph with n_slots slots gets.
+int choose_encoding(const HostCSR &g, int64_t n_slots);
+
+// enc: entry encoding; kmax: chunks each lane prefetches (see kmax_for); a
+// row of degree d gets the fewest lanes G with d <= (4 * kmax * G) >> bin_shift.
+int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors, int enc, int kmax,
+                 int bin_shift, HostLayout *out, std::string *msg);
+
+// Phases of a sweep as runs of consecutive colour classes: [cls[i], cls[i+1]).
+// Deterministic mode uses one class per phase.  Async mode keeps every class
+// holding at least 1/merge_div of the vertices on its own and merges runs of
+// smaller consecutive classes until they reach that size (merge_div = 0:
+// no merging).
+std::vector<int32_t> phase_classes(const HostLayout &L, const std::vector<int64_t> &class_size, int merge_div);
 
 // Splits each phase's items over nw wavefronts in contiguous runs of about
 // equal cost.  Returns [n_phases][nw + 1] item offsets.
-std::vector<uint32_t> partition_waves(const HostLayout &L, int32_t nw);
+std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int32_t> &phase_cls, int32_t nw);
 
 // Verifies that every item addresses only memory inside the layout (index
 // ranges of entries, slots and spin words).  Returns false with a message.

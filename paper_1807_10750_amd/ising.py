@@ -55,7 +55,7 @@ class Info(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_int64), ("n_colors", ctypes.c_int32),
                 ("replicas_per_group", ctypes.c_int32), ("n_groups", ctypes.c_int32),
                 ("uses_lds", ctypes.c_int32), ("grid", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("pm1", ctypes.c_int32), ("edge_bytes", ctypes.c_int64),
+                ("pm1", ctypes.c_int32), ("encoding", ctypes.c_int32), ("edge_bytes", ctypes.c_int64),
                 ("vertex_bytes", ctypes.c_int64), ("spin_bytes", ctypes.c_int64),
                 ("items", ctypes.c_int64)]
 

@@ -172,13 +172,27 @@ def test_user_spins_and_resume(I):
     assert_same(I, g, seed=9, ps=0.3, pe=0.05, M=50, R=5, spins=s0, t_begin=20, t_end=50)
 
 
-@pytest.mark.parametrize("knobs", [dict(ISING_GRID=1), dict(ISING_GRID=3), dict(ISING_GRID=64),
-                                   dict(ISING_NO_LDS=1), dict(ISING_NO_LDS=1, ISING_GRID=5),
-                                   dict(ISING_LONG_DEG=4), dict(ISING_LONG_DEG=4, ISING_GRID=2)])
-def test_launch_configuration_invariance(I, knobs):
-    g = G.powerlaw_chung_lu(6000, max_deg=500, seed=12)
+KNOBS = [dict(ISING_GRID=1), dict(ISING_GRID=3), dict(ISING_GRID=64), dict(ISING_NO_LDS=1),
+         dict(ISING_NO_LDS=1, ISING_GRID=5), dict(ISING_BIN_SHIFT=2), dict(ISING_BIN_SHIFT=4, ISING_GRID=2),
+         dict(ISING_BIN_SHIFT=6, ISING_GRID=7)]
+
+
+@pytest.mark.parametrize("knobs", KNOBS)
+@pytest.mark.parametrize("weights", ["pm1", "int8"])
+def test_launch_configuration_invariance(I, knobs, weights):
+    g = G.powerlaw_chung_lu(6000, max_deg=500, weights=weights, seed=12)
     with env(**knobs):
         assert_same(I, g, seed=13, ps=0.2, pe=0.0, M=25, R=3)
+
+
+@pytest.mark.parametrize("knobs", [dict(ISING_WIDE=1), dict(ISING_WIDE=1, ISING_GRID=4),
+                                   dict(ISING_WIDE=1, ISING_NO_LDS=1, ISING_BIN_SHIFT=3)])
+@pytest.mark.parametrize("R", [1, 5, 16])
+def test_wide_weight_stream(I, knobs, R):
+    g = G.powerlaw_chung_lu(4000, max_deg=300, weights="int8", seed=14)
+    with env(**knobs):
+        info = assert_same(I, g, seed=15, ps=0.2, pe=0.0, M=20, R=R)
+    assert info["encoding"] == 2
 
 
 def test_device_buffers(I):

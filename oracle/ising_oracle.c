@@ -29,10 +29,12 @@
  *   R5  F_p schedule: integer thresholds T_t; flip iff a 32-bit uniform
  *       x < T_t.  p -> T = min(2^32-1, floor(p * 2^32)), linear in t.
  *   R6  Exactly M sweeps; the last linear threshold is T_end.
- *   R7  RNG: Philox4x32-10 with key = seed.  The draw of vertex v, sweep t,
- *       replica r is word (r mod 4) of the block at counter {v, t, r div 4, 0},
- *       so one block serves four replicas (the paper only asks for one
- *       independent uniform per spin and sweep).
+ *   R7  RNG: Philox4x32-10 with key = seed.  The flip draw of vertex v,
+ *       sweep t, replica r is word (t mod 4) of the block at counter
+ *       {v, t div 4, r, 0}, so one block serves four consecutive sweeps; the
+ *       initial-spin draw of replica r is word (r mod 4) of the block at
+ *       {v, 0, r div 4, 1}.  The paper only asks for one independent
+ *       uniform per spin and sweep.
  *   R8  The RNG is keyed by the caller's vertex id.
  *   R9  Each unordered edge counted once in W, E and the cut.
  *   R10 Self-loops and duplicate edges are rejected; int8 weights; the
@@ -90,15 +92,23 @@ void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* The 32-bit draw of vertex v, sweep (or domain-0 index) t, replica r in
- * counter domain d: word (r mod 4) of Philox4x32-10 at counter
- * {v, t, r div 4, d}, key {lo(seed), hi(seed)} (reading R7). */
-static uint32_t draw(uint32_t v, uint32_t t, uint32_t r, uint32_t d, uint64_t seed) {
-  uint32_t ctr[4] = {v, t, r / 4u, d};
+/* Word w of Philox4x32-10 at counter {a, b, c, d}, key {lo(seed), hi(seed)}. */
+static uint32_t philox_word(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t w, uint64_t seed) {
+  uint32_t ctr[4] = {a, b, c, d};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t out[4];
   oracle_philox4x32_10(ctr, key, out);
-  return out[r % 4u];
+  return out[w];
+}
+
+/* Flip draw of vertex v in sweep t for replica r (reading R7). */
+static uint32_t flip_draw(uint32_t v, uint32_t t, uint32_t r, uint64_t seed) {
+  return philox_word(v, t / 4u, r, 0u, t % 4u, seed);
+}
+
+/* Initial-spin draw of vertex v for replica r (reading R7). */
+static uint32_t init_draw(uint32_t v, uint32_t r, uint64_t seed) {
+  return philox_word(v, 0u, r / 4u, 1u, r % 4u, seed);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -268,7 +278,7 @@ void oracle_order(int64_t n, const int32_t *color, int32_t n_colors, int32_t *or
 void oracle_init_spins(int64_t n, int32_t R, uint64_t seed, int8_t *spins) {
   for (int32_t r = 0; r < R; ++r)
     for (int64_t v = 0; v < n; ++v) {
-      uint32_t x = draw((uint32_t)v, 0u, (uint32_t)r, 1u, seed);
+      uint32_t x = init_draw((uint32_t)v, (uint32_t)r, seed);
       spins[(int64_t)r * n + v] = (x >> 31) ? 1 : -1;
     }
 }
@@ -294,7 +304,7 @@ static int8_t local_update(int32_t h, int8_t s) {
 /* by a sequential visit in the given order (the (colour, id) order makes   */
 /* this equal to any colour-phased parallel execution).  For each sweep t   */
 /* in [t_begin, t_end): update each vertex from its local field, then flip  */
-/* it when its domain-0 draw is below T[t] (R4, R5, R7).  T holds the whole */
+/* it when its flip draw is below T[t] (R4, R5, R7).  T holds the whole     */
 /* schedule (indexed by absolute sweep).                                    */
 /* ------------------------------------------------------------------------ */
 int oracle_anneal(int64_t n, const int64_t *row_ptr, const int32_t *col, const int8_t *w,
@@ -308,7 +318,7 @@ int oracle_anneal(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
         int64_t v = order[i];
         int32_t h = local_field(v, row_ptr, col, w, s);
         s[v] = local_update(h, s[v]);
-        if (draw((uint32_t)v, (uint32_t)t, (uint32_t)r, 0u, seed) < T[t]) s[v] = (int8_t)-s[v];
+        if (flip_draw((uint32_t)v, (uint32_t)t, (uint32_t)r, seed) < T[t]) s[v] = (int8_t)-s[v];
       }
     }
   }
@@ -329,7 +339,7 @@ int oracle_anneal_jacobi(int64_t n, const int64_t *row_ptr, const int32_t *col, 
       for (int64_t v = 0; v < n; ++v) {
         int32_t h = local_field(v, row_ptr, col, w, prev);
         int8_t x = local_update(h, prev[v]);
-        if (draw((uint32_t)v, (uint32_t)t, (uint32_t)r, 0u, seed) < T[t]) x = (int8_t)-x;
+        if (flip_draw((uint32_t)v, (uint32_t)t, (uint32_t)r, seed) < T[t]) x = (int8_t)-x;
         s[v] = x;
       }
     }

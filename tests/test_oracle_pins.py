@@ -61,14 +61,14 @@ def test_init_spins_use_domain1_bit31(aten_philox):
 def test_isolated_vertices_flip_by_counter(aten_philox):
     # With no edges the field is 0, the update keeps the spin, and only the
     # random flips act: spin_v(end) = s0_v * prod_t (-1 if x(v,t,r) < T[t]),
-    # x = word (r mod 4) of the block at counter {v, t, r div 4, 0}.
+    # x = word (t mod 4) of the block at counter {v, t div 4, r, 0}.
     n, R, M, seed = 9, 6, 30, 991
     g = G.empty(n)
     T = O.thresholds(0.9, 0.2, M)
     s0 = G.random_spins(n, R, 5)
-    rows = [[v, t, r // 4, 0, seed & 0xFFFFFFFF, seed >> 32]
+    rows = [[v, t // 4, r, 0, seed & 0xFFFFFFFF, seed >> 32]
             for r in range(R) for v in range(n) for t in range(M)]
-    words = np.repeat(np.arange(R) % 4, n * M)
+    words = np.tile(np.arange(M) % 4, R * n)
     x = aten_philox(rows)[np.arange(R * n * M), words].reshape(R, n, M)
     flips = (x < T[None, None, :].astype(np.uint64)).sum(axis=2)
     expect = (s0 * np.where(flips % 2 == 1, -1, 1)).astype(np.int8)
@@ -82,7 +82,7 @@ def test_flip_needs_draw_strictly_below_threshold(aten_philox):
     # false there, so that sweep must not flip it; T = x + 1 must flip it.
     seed, t = 12345, 3
     g = G.empty(1)
-    x = int(aten_philox([[0, t, 0, 0, seed & 0xFFFFFFFF, seed >> 32]])[0, 0])  # replica 0: word 0
+    x = int(aten_philox([[0, t // 4, 0, 0, seed & 0xFFFFFFFF, seed >> 32]])[0, t % 4])
     col, nc = O.color(g)
     o = O.order(col, nc)
     s0 = np.ones((1, 1), np.int8)

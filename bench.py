@@ -52,12 +52,13 @@ def make_graph(name):
 def algorithmic_bytes_per_sweep(g, info):
     """Bytes one sweep of one replica group must move in this layout.
 
-    Per directed edge: the 4-byte entry (neighbour slot, and the weight's sign
-    when every weight is +-1) plus 1 byte of weight otherwise.  Per vertex:
+    Per directed edge: the 4-byte entry (neighbour slot with the weight's sign
+    or the int8 weight packed in), plus 1 byte of weight for graphs too large
+    to pack it.  Per vertex:
     its 4-byte caller id (the flip counter) and the write of its new spin
     mask (L bits).  Padding and work-item metadata are overhead, not counted.
     """
-    per_edge = 4 if info["pm1"] else 5
+    per_edge = 5 if info["encoding"] == 2 else 4
     L = info["replicas_per_group"]
     return g.nnz * per_edge + g.n * 4 + g.n * L / 8.0
 
@@ -97,7 +98,10 @@ def main():
     ap.add_argument("--coloring", default="ff", choices=["ff", "lf"])
     ap.add_argument("--sweeps", type=int, default=None, help="override the schedule length")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
+    ap.add_argument("--p-start", type=float, default=0.1, help="initial flip probability of the linear schedule")
     ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per anneal launch")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -105,6 +109,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe > 0:
+        src = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe << 20}), flush=True)
+        return
     from paper_1807_10750_amd import ising as I
 
     wl = WORKLOADS[args.workload]
@@ -130,7 +142,7 @@ def main():
     del rp, cl, ww
     info = gr.info()
     print(f"# create {create_s:.2f}s info={info}", file=sys.stderr, flush=True)
-    sch = I.make_schedule(0.1, 0.0, M)
+    sch = I.make_schedule(args.p_start, 0.0, M)
     cut = torch.zeros(R, dtype=torch.int64, device=dev)
     energy = torch.zeros(R, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
@@ -187,6 +199,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "name": args.workload, "n": g.n, "nnz": g.nnz,
                    "sweeps": M, "replicas": R, "mode": args.mode, "coloring": args.coloring,
+                   "p_start": args.p_start,
                    "colors": info["n_colors"], "grid": info["grid"], "block": info["block"],
                    "lds_spins": bool(info["uses_lds"]), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

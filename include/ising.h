@@ -168,6 +168,8 @@ typedef struct {
   int64_t vertex_bytes;     /* bytes of per-vertex data read once per sweep per group */
   int64_t spin_bytes;       /* bytes of one group's packed spin state */
   int64_t items;            /* wavefront work items per sweep */
+  int32_t bins;             /* batched mode: workgroups per replica group, each owning whole
+                               connected components (0: one cooperative launch) */
 } ising_info_t;
 
 ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info);

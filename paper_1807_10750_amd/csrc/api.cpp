@@ -96,6 +96,15 @@ struct ising_graph_s {
   int32_t *d_vid = nullptr;
   Item *d_items = nullptr;
   uint32_t *d_wave_ptr[2] = {nullptr, nullptr};  // per mode: [phases][nw + 1]
+  uint32_t *d_own_w64[2] = {nullptr, nullptr};   // per mode: [phases][grid][2]
+  uint32_t *d_local[2] = {nullptr, nullptr};     // per mode: phase runs in workgroup 0 alone
+  uint32_t *d_flips = nullptr;                   // 3 flip planes per replica group
+  // batched mode: one workgroup per (bin of whole components, replica group)
+  bool batch = false;
+  int batch_waves = 4;
+  size_t batch_lds = 0;
+  uint32_t *d_bin_wave_ptr = nullptr;            // [n_bins][colours][waves + 1]
+  uint32_t *d_bin_words = nullptr;               // [n_bins + 1]
   uint32_t *d_cls_w64[2] = {nullptr, nullptr};   // per mode: phase -> spin word range
   int32_t n_phases[2] = {0, 0};
   uint32_t *d_spins = nullptr;
@@ -128,7 +137,8 @@ ising_status_t dev_alloc(T **p, size_t bytes, const char *what) {
 
 void free_all(ising_graph_s *g) {
   void *bufs[] = {g->d_entries, g->d_wts4, g->d_vid, g->d_items, g->d_wave_ptr[0], g->d_wave_ptr[1],
-                  g->d_cls_w64[0], g->d_cls_w64[1],
+                  g->d_cls_w64[0], g->d_cls_w64[1], g->d_own_w64[0], g->d_own_w64[1], g->d_flips,
+                  g->d_local[0], g->d_local[1], g->d_bin_wave_ptr, g->d_bin_words,
                   g->d_spins, g->d_thr, g->d_bar, g->d_cut, g->d_stage};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
@@ -279,28 +289,58 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   } catch (const std::bad_alloc &) {
     return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed while colouring"));
   }
+  // Batched mode: a graph made of many small components (a batch of graphs)
+  // runs one workgroup per bin of whole components, with no grid barriers.
+  std::vector<int32_t> bin_of;
+  int32_t n_bins = 1;
+  int64_t max_bin_slots = 0;
+  const bool allow_lds = env_int("ISING_NO_LDS", 0) == 0;
+  if (allow_lds && env_int("ISING_NO_BATCH", 0) == 0 && n > 0) {
+    int64_t max_comp = 0;
+    try {
+      bin_of = pack_components(csr, std::max<int64_t>(64, env_int("ISING_BIN_VERTICES", 4096)), &n_bins, &max_comp);
+    } catch (const std::bad_alloc &) {
+      return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed while finding components"));
+    }
+    g->batch = n_bins >= 2 && max_comp <= 16384;
+    if (g->batch) {
+      std::vector<int64_t> cnt((size_t)n_bins * g->n_colors, 0);
+      for (int64_t v = 0; v < n; ++v) ++cnt[(size_t)bin_of[v] * g->n_colors + g->color[v]];
+      for (int32_t b = 0; b < n_bins; ++b) {
+        int64_t slots = 0;
+        for (int32_t c = 0; c < g->n_colors; ++c) slots += (cnt[(size_t)b * g->n_colors + c] + 63) / 64 * 64;
+        max_bin_slots = std::max(max_bin_slots, slots);
+      }
+    }
+  }
+  if (!g->batch) {
+    bin_of.clear();
+    n_bins = 1;
+  }
   // replica packing: as many replicas per pass as fit an LDS copy of the state
   int64_t n_slots = 0;
   std::vector<int64_t> class_size(g->n_colors, 0);
   for (int64_t v = 0; v < n; ++v) ++class_size[g->color[v]];
   for (int64_t c : class_size) n_slots += (c + 63) / 64 * 64;
   int L = pow2_at_least(n_replicas);
-  const bool allow_lds = env_int("ISING_NO_LDS", 0) == 0;
-  auto state_bytes = [&](int l) { return (size_t)n_slots * (size_t)l / 8; };
-  while (allow_lds && L > 1 && state_bytes(L) > kLdsBudget) L >>= 1;
-  g->use_lds = allow_lds && state_bytes(L) <= kLdsBudget;
+  const size_t budget = g->batch ? (size_t)64 * 1024 : kLdsBudget;
+  const int64_t lds_slots = g->batch ? max_bin_slots : n_slots;
+  auto state_bytes = [&](int l) { return (size_t)lds_slots * (size_t)l / 8; };
+  while (allow_lds && L > 1 && state_bytes(L) > budget) L >>= 1;
+  g->use_lds = allow_lds && state_bytes(L) <= budget;
   if (!g->use_lds) L = pow2_at_least(n_replicas);
   const int bin_shift = (int)std::min<int64_t>(8, std::max<int64_t>(0, env_int("ISING_BIN_SHIFT", 0)));
   int enc = choose_encoding(csr, n_slots);
   if (enc == kEncW8 && env_int("ISING_WIDE", 0) != 0) enc = kEncWide;
-  v = build_layout(csr, g->color, g->n_colors, enc, kmax_for(L, enc), bin_shift, &g->lay, &msg);
+  v = build_layout(csr, g->color, g->n_colors, g->batch ? bin_of.data() : nullptr, n_bins, enc, kmax_for(L, enc),
+                   bin_shift, &g->lay, &msg);
   if (v != kPrepOk) return bail(fail((ising_status_t)v, msg));
   if (!check_layout(g->lay, &msg)) return bail(fail(ISING_ERR_DEVICE, "internal layout check: " + msg));
   HostLayout &lay = g->lay;
   g->L = L;
   g->n_groups = (n_replicas + L - 1) / L;
   g->n_words = (uint32_t)((size_t)lay.n_slots * (size_t)L / 32);
-  g->lds_bytes = g->use_lds ? std::max<size_t>(state_bytes(L), 16) : 0;
+  g->lds_bytes = g->use_lds && !g->batch ? std::max<size_t>((size_t)n_slots * L / 8, 16) : 0;
 
   // grid: enough workgroups for the largest colour class, at most what is co-resident
   int per_cu = 0;
@@ -324,15 +364,45 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   if (want > 0) grid = (int)std::min<int64_t>(want, max_grid);
   g->grid = grid;
   g->nw = grid * waves_per_block;
-  // phase tables: deterministic = one colour class per phase; async merges small classes
-  std::vector<uint32_t> wave_ptr[2], cls_w64[2];
-  const int merge_div = (int)env_int("ISING_ASYNC_MERGE", 32);
+  // phase tables: deterministic = one colour class per phase; async merges small classes.
+  // With several workgroups, deterministic phases of at most local_items items
+  // run in workgroup 0 alone, separated by workgroup syncs instead of grid barriers.
+  std::vector<uint32_t> wave_ptr[2], cls_w64[2], own_w64[2], local[2];
+  const int merge_div = (int)env_int("ISING_ASYNC_MERGE", 2);
+  const int64_t local_items = env_int("ISING_LOCAL_ITEMS", 0);  // measured slower on MI355X; off by default
   for (int m = 0; m < 2; ++m) {
     const std::vector<int32_t> pc = phase_classes(lay, class_size, m == 0 ? 0 : merge_div);
     g->n_phases[m] = (int32_t)pc.size() - 1;
-    wave_ptr[m] = partition_waves(lay, pc, g->nw);
+    local[m].assign(g->n_phases[m], 0u);
+    if (m == 0 && g->grid > 1)
+      for (int32_t p = 0; p < g->n_phases[m]; ++p)
+        local[m][p] = (int64_t)(lay.phase_items[pc[p + 1]] - lay.phase_items[pc[p]]) <= local_items ? 1u : 0u;
+    wave_ptr[m] = partition_waves(lay, pc, g->nw, local[m], waves_per_block);
+    own_w64[m] = own_words(lay, wave_ptr[m], g->n_phases[m], g->grid, waves_per_block, L);
     cls_w64[m].resize(pc.size());
     for (size_t p = 0; p < pc.size(); ++p) cls_w64[m][p] = (uint32_t)((uint64_t)lay.cls_begin[pc[p]] * L / 64);
+  }
+
+  // batched mode tables
+  std::vector<uint32_t> bin_wave_ptr, bin_words;
+  if (g->batch) {
+    g->batch_waves = (int)env_int("ISING_BATCH_WAVES", 4);
+    if (g->batch_waves != 4 && g->batch_waves != 8 && g->batch_waves != 16) g->batch_waves = 4;
+    const int32_t nc = g->n_colors;
+    std::vector<uint32_t> none((size_t)nc, 0u);
+    bin_words.resize((size_t)n_bins + 1);
+    size_t max_words = 0;
+    for (int32_t b = 0; b < n_bins; ++b) {
+      std::vector<int32_t> pc((size_t)nc + 1);
+      for (int32_t c = 0; c <= nc; ++c) pc[c] = b * nc + c;
+      const std::vector<uint32_t> wp = partition_waves(lay, pc, g->batch_waves, none, g->batch_waves);
+      bin_wave_ptr.insert(bin_wave_ptr.end(), wp.begin(), wp.end());
+      bin_words[b] = (uint32_t)((uint64_t)lay.cls_begin[(size_t)b * nc] * L / 32);
+      const uint64_t end = (uint64_t)lay.cls_begin[(size_t)(b + 1) * nc] * L / 32;
+      max_words = std::max<size_t>(max_words, (size_t)(end - bin_words[b]));
+    }
+    bin_words[n_bins] = (uint32_t)((uint64_t)lay.n_slots * L / 32);
+    g->batch_lds = std::max<size_t>(max_words * 4, 16);
   }
 
   // device buffers
@@ -352,11 +422,32 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
     if ((r = dev_alloc(&g->d_wave_ptr[m], sizeof(uint32_t) * wave_ptr[m].size(), "wave table")) != ISING_OK) return bail(r);
     if ((r = upload(g->d_wave_ptr[m], wave_ptr[m].data(), sizeof(uint32_t) * wave_ptr[m].size(), "wave upload")) != ISING_OK)
       return bail(r);
+    if ((r = dev_alloc(&g->d_local[m], sizeof(uint32_t) * (local[m].size() + 1), "local-phase table")) != ISING_OK)
+      return bail(r);
+    if ((r = upload(g->d_local[m], local[m].data(), sizeof(uint32_t) * local[m].size(), "local-phase upload")) != ISING_OK)
+      return bail(r);
+    if ((r = dev_alloc(&g->d_own_w64[m], sizeof(uint32_t) * own_w64[m].size(), "ownership table")) != ISING_OK)
+      return bail(r);
+    if ((r = upload(g->d_own_w64[m], own_w64[m].data(), sizeof(uint32_t) * own_w64[m].size(), "ownership upload")) !=
+        ISING_OK)
+      return bail(r);
     if ((r = dev_alloc(&g->d_cls_w64[m], sizeof(uint32_t) * cls_w64[m].size(), "class table")) != ISING_OK) return bail(r);
     if ((r = upload(g->d_cls_w64[m], cls_w64[m].data(), sizeof(uint32_t) * cls_w64[m].size(), "class upload")) != ISING_OK)
       return bail(r);
   }
   if ((r = dev_alloc(&g->d_spins, sizeof(uint32_t) * (size_t)g->n_words * g->n_groups, "spins")) != ISING_OK) return bail(r);
+  if ((r = dev_alloc(&g->d_flips, sizeof(uint32_t) * 3 * (size_t)g->n_words * g->n_groups, "flip planes")) != ISING_OK)
+    return bail(r);
+  if (g->batch) {
+    if ((r = dev_alloc(&g->d_bin_wave_ptr, sizeof(uint32_t) * bin_wave_ptr.size(), "bin wave table")) != ISING_OK)
+      return bail(r);
+    if ((r = upload(g->d_bin_wave_ptr, bin_wave_ptr.data(), sizeof(uint32_t) * bin_wave_ptr.size(), "bin wave upload")) !=
+        ISING_OK)
+      return bail(r);
+    if ((r = dev_alloc(&g->d_bin_words, sizeof(uint32_t) * bin_words.size(), "bin word table")) != ISING_OK) return bail(r);
+    if ((r = upload(g->d_bin_words, bin_words.data(), sizeof(uint32_t) * bin_words.size(), "bin word upload")) != ISING_OK)
+      return bail(r);
+  }
   if ((r = dev_alloc(&g->d_bar, sizeof(uint32_t) * kBarWords, "flags")) != ISING_OK) return bail(r);
   if ((r = dev_alloc(&g->d_cut, sizeof(unsigned long long) * 2 * (size_t)n_replicas + 16, "cut")) != ISING_OK) return bail(r);
   if ((r = dev_alloc(&g->d_stage, (size_t)n * (size_t)n_replicas, "spin staging")) != ISING_OK) return bail(r);
@@ -390,8 +481,9 @@ ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info) {
   info->replicas_per_group = g->L;
   info->n_groups = g->n_groups;
   info->uses_lds = g->use_lds ? 1 : 0;
-  info->grid = g->grid;
-  info->block = kAnnealBlock;
+  info->grid = g->batch ? g->lay.n_bins * g->n_groups : g->grid;
+  info->block = g->batch ? 64 * g->batch_waves : kAnnealBlock;
+  info->bins = g->batch ? g->lay.n_bins : 0;
   info->pm1 = g->lay.enc == kEncPm1 ? 1 : 0;
   info->encoding = g->lay.enc;
   info->edge_bytes = g->entry_bytes;
@@ -510,6 +602,8 @@ ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *s, uint64_t 
   a.items = g->d_items;
   const int m = mode == ISING_MODE_ASYNC ? 1 : 0;
   a.wave_ptr = g->d_wave_ptr[m];
+  a.own_w64 = g->d_own_w64[m];
+  a.local = g->d_local[m];
   a.cls_w64 = g->d_cls_w64[m];
   a.thr = g->d_thr;
   a.bar = g->d_bar;
@@ -520,12 +614,27 @@ ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *s, uint64_t 
   a.seed_lo = (uint32_t)seed;
   a.seed_hi = (uint32_t)(seed >> 32);
   a.spin_limit = (uint32_t)std::max<int64_t>(1000, env_int("ISING_BARRIER_POLLS", 20000000));
+  if (g->batch) {
+    a.spins = g->d_spins;
+    a.flips = g->d_flips;
+    a.wave_ptr = g->d_bin_wave_ptr;
+    a.bin_words = g->d_bin_words;
+    a.n_bins = g->lay.n_bins;
+    a.n_phases = g->n_colors;
+    a.r_total = (uint32_t)g->R;
+    a.t_begin = sweep_begin;
+    a.t_end = sweep_end;
+    HIP_TRY(launch_anneal_batch(g->L, g->lay.enc, g->batch_waves, a, g->lay.n_bins * g->n_groups, g->batch_lds, st),
+            "batched anneal launch");
+    return ISING_OK;
+  }
   // keep the barrier counter below 2^31 within one launch
   const int64_t barriers_per_sweep = g->grid > 1 ? (a.async_mode ? 1 : std::max(1, a.n_phases)) : 0;
   int64_t chunk = sweep_end - sweep_begin;
   if (barriers_per_sweep > 0) chunk = std::max<int64_t>(1, ((int64_t)1 << 30) / (barriers_per_sweep * g->grid));
   for (int grp = 0; grp < g->n_groups; ++grp) {
     a.spins = g->d_spins + (size_t)grp * g->n_words;
+    a.flips = g->d_flips + (size_t)grp * 3 * g->n_words;
     a.r0 = (uint32_t)(grp * g->L);
     a.r_count = group_r_count(g, grp);
     for (int64_t t0 = sweep_begin; t0 < sweep_end; t0 += chunk) {

@@ -73,47 +73,46 @@ __device__ __forceinline__ uint32_t lmask() {
   return L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
 }
 
-// Mask of slot s from a word array (LDS or global).
+// Mask of slot s from a word array (LDS or global) that starts at spin word woff.
 template <int L, typename P>
-__device__ __forceinline__ uint32_t mask_of(P words, uint32_t s) {
+__device__ __forceinline__ uint32_t mask_of(P words, uint32_t s, uint32_t woff = 0) {
   const uint32_t bit = s * L;
-  return (words[bit >> 5] >> (bit & 31)) & lmask<L>();
+  return (words[(bit >> 5) - woff] >> (bit & 31)) & lmask<L>();
 }
 
 // Adds the contribution of one edge entry to the L field accumulators
 // (entry encodings: see layout.h; wv is the separate weight of kEncWide).
 template <int L, int ENC, typename P>
-__device__ __forceinline__ void accumulate(int32_t (&h)[L], uint32_t x, int32_t wv, P words) {
+__device__ __forceinline__ void accumulate(int32_t (&h)[L], uint32_t x, int32_t wv, P words, uint32_t woff) {
   if (ENC == kEncPm1) {
     const bool valid = x != kSentinel;
     const uint32_t slot = valid ? (x & ~kSignBit) : 0u;
-    uint32_t m = mask_of<L>(words, slot);
+    uint32_t m = mask_of<L>(words, slot, woff);
     if (x & kSignBit) m = ~m;
 #pragma unroll
     for (int j = 0; j < L; ++j) h[j] += valid ? (int32_t)(((m >> j) & 1u) << 1) - 1 : 0;
   } else {
     const uint32_t slot = ENC == kEncW8 ? (x & 0xFFFFFFu) : x;
     const int32_t w = ENC == kEncW8 ? (int32_t)(int8_t)(x >> 24) : wv;
-    const uint32_t m = mask_of<L>(words, slot);
+    const uint32_t m = mask_of<L>(words, slot, woff);
 #pragma unroll
     for (int j = 0; j < L; ++j) h[j] += ((m >> j) & 1u) ? w : -w;
   }
 }
 
 template <int L, int ENC, typename P>
-__device__ __forceinline__ void accumulate4(int32_t (&h)[L], const uint4 &x, uint32_t wv, P words) {
-  accumulate<L, ENC>(h, x.x, (int32_t)(int8_t)(wv), words);
-  accumulate<L, ENC>(h, x.y, (int32_t)(int8_t)(wv >> 8), words);
-  accumulate<L, ENC>(h, x.z, (int32_t)(int8_t)(wv >> 16), words);
-  accumulate<L, ENC>(h, x.w, (int32_t)(int8_t)(wv >> 24), words);
+__device__ __forceinline__ void accumulate4(int32_t (&h)[L], const uint4 &x, uint32_t wv, P words, uint32_t woff) {
+  accumulate<L, ENC>(h, x.x, (int32_t)(int8_t)(wv), words, woff);
+  accumulate<L, ENC>(h, x.y, (int32_t)(int8_t)(wv >> 8), words, woff);
+  accumulate<L, ENC>(h, x.z, (int32_t)(int8_t)(wv >> 16), words, woff);
+  accumulate<L, ENC>(h, x.w, (int32_t)(int8_t)(wv >> 24), words, woff);
 }
 
-// Local update (Eq. 2 with J = -w, a zero field keeps the spin) and the
-// annealing flip of every replica bit.  The draw of replica r is word
-// (r mod 4) of the Philox block at counter {v, t, r div 4, 0}.
+// Local update (Eq. 2 with J = -w, a zero field keeps the spin) of every
+// replica bit, then the annealing flips (bit j set = flip replica j).
+// Padding slots have no edges and draw no flips; their bits are never read.
 template <int L>
-__device__ __forceinline__ uint32_t update_mask(const int32_t (&h)[L], uint32_t own, int32_t v, uint32_t t,
-                                                uint32_t T, const AnnealArgs &a) {
+__device__ __forceinline__ uint32_t update_mask(const int32_t (&h)[L], uint32_t own, uint32_t flips) {
   uint32_t nm = 0;
 #pragma unroll
   for (int j = 0; j < L; ++j) {
@@ -121,27 +120,36 @@ __device__ __forceinline__ uint32_t update_mask(const int32_t (&h)[L], uint32_t 
     s = h[j] > 0 ? 0u : (h[j] < 0 ? 1u : s);
     nm |= s << j;
   }
-  if (v < 0) return 0u;
-  if (T != 0u) {
-    const uint32_t live = a.r_count >= 32u ? 0xFFFFFFFFu : ((1u << a.r_count) - 1u);
-    uint32_t flips = 0;
-    if (L >= 4) {
+  return (nm ^ flips) & lmask<L>();
+}
+
+// Flip draws of sweep t (reading: word t mod 4 of the Philox block at counter
+// {v, t div 4, r, 0}).  Returns this sweep's flip bits; the bits of the
+// block's later sweeps t' < t_end are returned in later[0..2] (index t' mod 4 - 1).
+template <int L>
+__device__ __forceinline__ uint32_t draw_flips(int32_t v, uint32_t t, const AnnealArgs &a, uint32_t (&later)[3]) {
+  const uint32_t b = t >> 2, w = t & 3u;
+  uint32_t Tk[4];
 #pragma unroll
-      for (int jj = 0; jj < L / 4; ++jj) {
-        if ((uint32_t)(4 * jj) < a.r_count) {
-          const uint4 x = philox4((uint32_t)v, t, (a.r0 >> 2) + (uint32_t)jj, 0u, a.seed_lo, a.seed_hi);
-          const uint32_t f = (x.x < T ? 1u : 0u) | (x.y < T ? 2u : 0u) | (x.z < T ? 4u : 0u) | (x.w < T ? 8u : 0u);
-          flips |= f << (4 * jj);
-        }
-      }
-    } else {
-      const uint4 x = philox4((uint32_t)v, t, a.r0 >> 2, 0u, a.seed_lo, a.seed_hi);
-#pragma unroll
-      for (int j = 0; j < L; ++j) flips |= (word_of(x, (a.r0 + (uint32_t)j) & 3u) < T ? 1u : 0u) << j;
-    }
-    nm ^= flips & live;
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t tk = 4u * b + (uint32_t)k;
+    Tk[k] = ((uint32_t)k >= w && (int64_t)tk < a.t_end) ? a.thr[tk] : 0u;
   }
-  return nm & lmask<L>();
+  uint32_t now = 0;
+  later[0] = later[1] = later[2] = 0u;
+  if (v < 0 || (Tk[0] | Tk[1] | Tk[2] | Tk[3]) == 0u) return 0u;
+#pragma unroll 1
+  for (int j = 0; j < L; ++j) {
+    if ((uint32_t)j < a.r_count) {
+      const uint4 x = philox4((uint32_t)v, b, a.r0 + (uint32_t)j, 0u, a.seed_lo, a.seed_hi);
+      const uint32_t f0 = x.x < Tk[0], f1 = x.y < Tk[1], f2 = x.z < Tk[2], f3 = x.w < Tk[3];
+      now |= (w == 0 ? f0 : w == 1 ? f1 : w == 2 ? f2 : f3) << j;
+      later[0] |= f1 << j;
+      later[1] |= f2 << j;
+      later[2] |= f3 << j;
+    }
+  }
+  return now;
 }
 
 template <typename T>
@@ -207,18 +215,21 @@ struct Fetched {
   uint32_t w[KW];  // separate weights (kEncWide only)
   int32_t vid;
   uint32_t ownw;   // the coherent spin word holding this lane's row
+  uint32_t flipw;  // stored flip bits of this sweep (sweeps not divisible by 4)
 };
 
 // Issues every load of one item: this lane's row id, its spin word and its
 // share of the sliced-ELL chunks (chunks g, g + G, ...).
+// plane: flip plane to read for this item's sweep (-1 when the sweep draws).
 template <int L, int ENC>
-__device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it, int lane, Fetched<L, ENC> &f) {
+__device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it, int lane, Fetched<L, ENC> &f, int plane) {
   constexpr int KM = Fetched<L, ENC>::KM;
   const uint32_t G = it.g, K = 64u / G;
   const uint32_t r = (uint32_t)lane / G, gl = (uint32_t)lane & (G - 1u);
   const uint32_t slot = it.id + r;
-  f.vid = a.vid[slot];
+  f.vid = plane < 0 ? a.vid[slot] : 0;  // the caller id only keys the Philox draws
   f.ownw = ld_coherent(a.spins + ((slot * L) >> 5));
+  f.flipw = plane >= 0 ? ld_coherent(a.flips + (size_t)plane * a.n_words + ((slot * L) >> 5)) : 0u;
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
     const uint32_t q = gl + (uint32_t)k * G;
@@ -233,9 +244,12 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it, int l
   }
 }
 
+// draws: this sweep computes the Philox blocks (t divisible by 4, or the
+// first sweep of the call); otherwise the flip bits come from the planes.
+// woff: the spin word that lds[0] holds (0 when LDS mirrors the whole state).
 template <int L, int ENC, bool USE_LDS>
 __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it, int lane, const Fetched<L, ENC> &f,
-                                        uint32_t *lds, uint32_t t, uint32_t T) {
+                                        uint32_t *lds, uint32_t t, bool draws, uint32_t woff = 0) {
   constexpr int KM = Fetched<L, ENC>::KM;
   const uint32_t G = it.g, K = 64u / G;
   const uint32_t r = (uint32_t)lane / G, gl = (uint32_t)lane & (G - 1u);
@@ -248,28 +262,43 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it, int
     if (gl + (uint32_t)k * G < it.len4) {
       const uint32_t wv = ENC == kEncWide ? f.w[k < Fetched<L, ENC>::KW ? k : 0] : 0u;
       if (USE_LDS)
-        accumulate4<L, ENC>(h, f.e[k], wv, lds);
+        accumulate4<L, ENC>(h, f.e[k], wv, lds, woff);
       else
-        accumulate4<L, ENC>(h, f.e[k], wv, a.spins);
+        accumulate4<L, ENC>(h, f.e[k], wv, a.spins, 0u);
     }
   }
-  // rows longer than the prefetch depth: the rest of the chunks
-  for (uint32_t q = gl + (uint32_t)KM * G; q < it.len4; q += G) {
-    const size_t idx = (size_t)it.base4 + (size_t)q * K + r;
-    const uint4 x = a.entries[idx];
-    const uint32_t wv = ENC == kEncWide ? a.wts4[idx] : 0u;
-    if (USE_LDS)
-      accumulate4<L, ENC>(h, x, wv, lds);
-    else
-      accumulate4<L, ENC>(h, x, wv, a.spins);
+  // rows longer than the prefetch depth: the rest of the chunks, four loads in flight
+  for (uint32_t q0 = gl + (uint32_t)KM * G; q0 < it.len4; q0 += 4u * G) {
+    uint4 x[4];
+    uint32_t wv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t q = q0 + (uint32_t)k * G;
+      const size_t idx = (size_t)it.base4 + (size_t)(q < it.len4 ? q : q0) * K + r;
+      x[k] = a.entries[idx];
+      wv[k] = ENC == kEncWide ? a.wts4[idx] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (q0 + (uint32_t)k * G < it.len4) {
+        if (USE_LDS)
+          accumulate4<L, ENC>(h, x[k], wv[k], lds, woff);
+        else
+          accumulate4<L, ENC>(h, x[k], wv[k], a.spins, 0u);
+      }
+    }
   }
   for (uint32_t off = 1; off < G; off <<= 1) {
 #pragma unroll
     for (int j = 0; j < L; ++j) h[j] += __shfl_xor(h[j], (int)off);
   }
   const uint32_t bit0 = slot * L;
-  const uint32_t own = (f.ownw >> (bit0 & 31)) & lmask<L>();
-  const uint32_t nm = update_mask<L>(h, own, f.vid, t, T, a);
+  const uint32_t sh = bit0 & 31;
+  const uint32_t own = (f.ownw >> sh) & lmask<L>();
+  uint32_t later[3];
+  const uint32_t flips =
+      draws ? draw_flips<L>(f.vid, t, a, later) : ((f.flipw >> sh) & lmask<L>());
+  const uint32_t nm = update_mask<L>(h, own, flips);
   const bool rep = gl == 0u;
   if (K * L >= 32u) {
     // the item owns whole words: plain coherent stores
@@ -277,24 +306,61 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it, int
       const unsigned long long b = __ballot(nm & 1u);
       if (lane == 0) {
         st_coherent64(reinterpret_cast<unsigned long long *>(a.spins) + (it.id >> 6), b);
-        if (USE_LDS) reinterpret_cast<unsigned long long *>(lds)[it.id >> 6] = b;
+        if (USE_LDS) reinterpret_cast<unsigned long long *>(lds)[(it.id >> 6) - (woff >> 1)] = b;
+      }
+      if (draws) {
+        const uint32_t first = t & 3u;  // planes first .. 2 hold sweeps first+1 .. 3
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if ((uint32_t)k < first) continue;
+          const unsigned long long fb = __ballot(later[k] & 1u);
+          if (lane == 0)
+            st_coherent64(reinterpret_cast<unsigned long long *>(a.flips + (size_t)k * a.n_words) + (it.id >> 6), fb);
+        }
       }
     } else {
       constexpr uint32_t P = 32u / L;  // rows per word
-      uint32_t val = rep ? nm << (bit0 & 31) : 0u;
+      uint32_t val = rep ? nm << sh : 0u;
       for (uint32_t off = G; off < G * P; off <<= 1) val |= __shfl_xor(val, (int)off);
       if (rep && (r % P) == 0u) {
         st_coherent(a.spins + (bit0 >> 5), val);
-        if (USE_LDS) lds[bit0 >> 5] = val;
+        if (USE_LDS) lds[(bit0 >> 5) - woff] = val;
+      }
+      if (draws) {
+        const uint32_t first = t & 3u;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if ((uint32_t)k < first) continue;
+          uint32_t fv = rep ? later[k] << sh : 0u;
+          for (uint32_t off = G; off < G * P; off <<= 1) fv |= __shfl_xor(fv, (int)off);
+          if (rep && (r % P) == 0u) st_coherent(a.flips + (size_t)k * a.n_words + (bit0 >> 5), fv);
+        }
       }
     }
   } else {
     // all K rows share one word with other items: exact XOR of the changes
-    uint32_t chg = rep ? (own ^ nm) << (bit0 & 31) : 0u;
+    uint32_t chg = rep ? (own ^ nm) << sh : 0u;
     for (uint32_t off = G; off < 64u; off <<= 1) chg |= __shfl_xor(chg, (int)off);
     if (lane == 0 && chg != 0u) {
       __hip_atomic_fetch_xor(a.spins + (bit0 >> 5), chg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (USE_LDS) atomicXor(lds + (bit0 >> 5), chg);
+      if (USE_LDS) atomicXor(lds + ((bit0 >> 5) - woff), chg);
+    }
+    if (draws) {
+      // this item's bits of the word: clear, then set
+      uint32_t span = rep ? lmask<L>() << sh : 0u;
+      for (uint32_t off = G; off < 64u; off <<= 1) span |= __shfl_xor(span, (int)off);
+      const uint32_t first = t & 3u;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if ((uint32_t)k < first) continue;
+        uint32_t fv = rep ? later[k] << sh : 0u;
+        for (uint32_t off = G; off < 64u; off <<= 1) fv |= __shfl_xor(fv, (int)off);
+        if (lane == 0) {
+          uint32_t *w = a.flips + (size_t)k * a.n_words + (bit0 >> 5);
+          __hip_atomic_fetch_and(w, ~span, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (fv != 0u) __hip_atomic_fetch_or(w, fv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
     }
   }
 }
@@ -318,72 +384,122 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   const bool multi = gridDim.x > 1;
   const bool fenced = !USE_LDS;
   const uint32_t n_grp = gridDim.x < 8u ? gridDim.x : 8u;
+  // two items in flight where the registers allow it
+  constexpr bool kDeep = ENC == kEncPm1 && L <= 8;
   if (USE_LDS) {
     restage(a, lds, 0, a.n_words / 2, threadIdx.x, blockDim.x);
     __syncthreads();
   }
   if (a.n_phases <= 0 || a.t_begin >= a.t_end) return;
+  // sweep t draws Philox blocks when t is divisible by 4 or starts the call;
+  // otherwise its flip bits sit in plane (t mod 4) - 1
+  auto plane_of = [&](int64_t t) -> int { return (t == a.t_begin || (t & 3) == 0) ? -1 : (int)(t & 3) - 1; };
   uint32_t epoch = 0;
+  uint32_t run_w = 0;  // first spin word written since the last grid barrier
   const size_t stride = (size_t)a.nw + 1;
   uint32_t ib = a.wave_ptr[gw], ie = a.wave_ptr[gw + 1];
-  Fetched<L, ENC> fa, fb;
+  Fetched<L, ENC> fa, fb, fc;
   Item ita;
   if (ib < ie) {
     ita = a.items[ib];
-    fetch<L, ENC>(a, ita, lane, fa);
+    fetch<L, ENC>(a, ita, lane, fa, plane_of(a.t_begin));
   }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
-    const uint32_t T = a.thr[t];
+    const int plane = plane_of(t);
     for (int32_t ph = 0; ph < a.n_phases; ++ph) {
-      // items of this phase, one ahead in flight
-      for (uint32_t i = ib; i < ie; ++i) {
-        const bool more = i + 1 < ie;
+      if (kDeep) {
+        // items of this phase, two ahead in flight
         Item itb;
-        if (more) {
-          itb = a.items[i + 1];
-          fetch<L, ENC>(a, itb, lane, fb);
+        if (ib + 1 < ie) {
+          itb = a.items[ib + 1];
+          fetch<L, ENC>(a, itb, lane, fb, plane);
         }
-        compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, T);
-        if (more) {
+        for (uint32_t i = ib; i < ie; ++i) {
+          Item itc;
+          if (i + 2 < ie) {
+            itc = a.items[i + 2];
+            fetch<L, ENC>(a, itc, lane, fc, plane);
+          }
+          compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
           ita = itb;
           fa = fb;
+          itb = itc;
+          fb = fc;
+        }
+      } else {
+        // items of this phase, one ahead in flight
+        for (uint32_t i = ib; i < ie; ++i) {
+          const bool more = i + 1 < ie;
+          Item itb;
+          if (more) {
+            itb = a.items[i + 1];
+            fetch<L, ENC>(a, itb, lane, fb, plane);
+          }
+          compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
+          if (more) {
+            ita = itb;
+            fa = fb;
+          }
         }
       }
       // the next phase's item range and first item
       const bool last_phase = ph + 1 == a.n_phases;
       const int32_t nph = last_phase ? 0 : ph + 1;
       const bool done = last_phase && t + 1 == a.t_end;
+      const int next_plane = last_phase ? plane_of(t + 1) : plane;
       ib = a.wave_ptr[(size_t)nph * stride + gw];
       ie = a.wave_ptr[(size_t)nph * stride + gw + 1];
       if (done) ie = ib;
       if (multi && !a.async_mode) {
-        // deterministic: barrier, then refresh the class just written
+        // deterministic.  A run of small phases goes to workgroup 0 alone,
+        // which separates them by workgroup syncs; every other phase, and
+        // the end of such a run, is a grid barrier after which all
+        // workgroups refresh the classes written since the previous one.
+        if (!a.local[ph]) run_w = a.cls_w64[ph];
+        if (a.local[ph] && a.local[nph] && !last_phase) {
+          if (blockIdx.x == 0) {
+            if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          }
+          if (ib < ie) {
+            ita = a.items[ib];
+            fetch<L, ENC>(a, ita, lane, fa, next_plane);
+          }
+          continue;
+        }
         bar_arrive(a.bar, fenced);
         if (ib < ie) {
           ita = a.items[ib];
-          fetch<L, ENC>(a, ita, lane, fa);
+          fetch<L, ENC>(a, ita, lane, fa, next_plane);
         }
         ++epoch;
         if (!bar_wait(a.bar, epoch * n_grp, a.spin_limit, fenced)) return;
         if (USE_LDS) {
-          restage(a, lds, a.cls_w64[ph], a.cls_w64[ph + 1], threadIdx.x, blockDim.x);
+          restage(a, lds, run_w, a.cls_w64[ph + 1], threadIdx.x, blockDim.x);
           __syncthreads();
         }
+        run_w = a.cls_w64[ph + 1];
       } else if (multi) {
-        // async: no grid-wide wait inside a sweep.  The workgroup drains its
-        // stores and meets, so no refresh can overwrite a fresher LDS word
-        // of its own, then each wave refreshes its share of the phase's
-        // classes from the global state and moves on.
-        if (USE_LDS) {
-          __builtin_amdgcn_s_waitcnt(0);
-          __syncthreads();
-        }
+        // async: no wait inside a sweep.  Each wave refreshes its share of
+        // the phase's spin words from the global state, skipping the words
+        // only this workgroup writes (its LDS copy of those is the freshest).
         if (ib < ie) {
           ita = a.items[ib];
-          fetch<L, ENC>(a, ita, lane, fa);
+          fetch<L, ENC>(a, ita, lane, fa, next_plane);
         }
-        if (USE_LDS)
-          restage(a, lds, a.cls_w64[ph], a.cls_w64[ph + 1], (uint32_t)(wib * kWave + lane), blockDim.x);
+        if (USE_LDS) {
+          const uint32_t *own = a.own_w64 + ((size_t)ph * gridDim.x + blockIdx.x) * 2;
+          const uint32_t b = a.cls_w64[ph], e = a.cls_w64[ph + 1];
+          const uint32_t ol = own[0] > b ? own[0] : b, oh = own[1] < e ? own[1] : e;
+          const uint32_t first = (uint32_t)(wib * kWave + lane);
+          if (ol < oh) {
+            restage(a, lds, b, ol, first, blockDim.x);
+            restage(a, lds, oh, e, first, blockDim.x);
+          } else {
+            restage(a, lds, b, e, first, blockDim.x);
+          }
+        }
         if (last_phase && !done) {
           // sweeps stay synchronised
           bar_arrive(a.bar, fenced);
@@ -394,7 +510,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         // one workgroup: its LDS copy is current
         if (ib < ie) {
           ita = a.items[ib];
-          fetch<L, ENC>(a, ita, lane, fa);
+          fetch<L, ENC>(a, ita, lane, fa, next_plane);
         }
         if (!a.async_mode || last_phase) {
           if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -402,6 +518,69 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched anneal: one workgroup per (bin, replica group).  A bin holds whole
+// connected components, so it never reads spins outside its own slot range:
+// its LDS copy covers only that range and is always current, colour phases
+// need only workgroup syncs, and workgroups never wait for each other.  The
+// result equals the single-launch anneal of the union graph.
+// ---------------------------------------------------------------------------
+template <int L, int ENC, int W>
+__global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
+  extern __shared__ uint32_t lds[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wib = threadIdx.x / kWave;
+  const uint32_t bin = blockIdx.x % (uint32_t)args.n_bins;
+  const uint32_t grp = blockIdx.x / (uint32_t)args.n_bins;
+  AnnealArgs a = args;
+  a.spins = args.spins + (size_t)grp * args.n_words;
+  a.flips = args.flips + (size_t)grp * 3 * args.n_words;
+  a.r0 = grp * (uint32_t)L;
+  a.r_count = args.r_total - a.r0 < (uint32_t)L ? args.r_total - a.r0 : (uint32_t)L;
+  const uint32_t w0 = args.bin_words[bin], w1 = args.bin_words[bin + 1];
+  for (uint32_t i = threadIdx.x; i < w1 - w0; i += blockDim.x) lds[i] = ld_coherent(a.spins + w0 + i);
+  __syncthreads();
+  if (a.n_phases <= 0 || a.t_begin >= a.t_end) return;
+  auto plane_of = [&](int64_t t) -> int { return (t == a.t_begin || (t & 3) == 0) ? -1 : (int)(t & 3) - 1; };
+  const uint32_t *wp = a.wave_ptr + (size_t)bin * a.n_phases * (W + 1) + wib;
+  uint32_t ib = wp[0], ie = wp[1];
+  Fetched<L, ENC> fa, fb;
+  Item ita;
+  if (ib < ie) {
+    ita = a.items[ib];
+    fetch<L, ENC>(a, ita, lane, fa, plane_of(a.t_begin));
+  }
+  for (int64_t t = a.t_begin; t < a.t_end; ++t) {
+    const int plane = plane_of(t);
+    for (int32_t ph = 0; ph < a.n_phases; ++ph) {
+      for (uint32_t i = ib; i < ie; ++i) {
+        const bool more = i + 1 < ie;
+        Item itb;
+        if (more) {
+          itb = a.items[i + 1];
+          fetch<L, ENC>(a, itb, lane, fb, plane);
+        }
+        compute<L, ENC, true>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, w0);
+        if (more) {
+          ita = itb;
+          fa = fb;
+        }
+      }
+      const bool last_phase = ph + 1 == a.n_phases;
+      const int32_t nph = last_phase ? 0 : ph + 1;
+      const bool done = last_phase && t + 1 == a.t_end;
+      ib = wp[(size_t)nph * (W + 1)];
+      ie = wp[(size_t)nph * (W + 1) + 1];
+      if (done) ie = ib;
+      if (ib < ie) {
+        ita = a.items[ib];
+        fetch<L, ENC>(a, ita, lane, fa, last_phase ? plane_of(t + 1) : plane);
+      }
+      if (!a.async_mode || last_phase) __syncthreads();
     }
   }
 }
@@ -554,6 +733,15 @@ hipError_t launch_anneal_t(const AnnealArgs &a, int grid, size_t lds_bytes, hipS
                                     args, USE_LDS ? (unsigned)lds_bytes : 0u, s);
 }
 
+template <int L, int ENC, int W>
+hipError_t launch_batch_t(const AnnealArgs &a, int grid, size_t lds_bytes, hipStream_t s) {
+  auto kern = k_anneal_batch<L, ENC, W>;
+  hipError_t e = set_lds_limit(kern, lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(W * kWave), (unsigned)lds_bytes, s, a);
+  return hipGetLastError();
+}
+
 template <int L, int ENC, bool USE_LDS>
 hipError_t occupancy_t(int *blocks, size_t lds_bytes) {
   auto kern = k_anneal<L, ENC, USE_LDS>;
@@ -588,6 +776,21 @@ hipError_t anneal_L(const AnnealArgs &a, int enc, bool use_lds, int grid, size_t
   if (enc == kEncPm1) return anneal_LE<L, kEncPm1>(a, use_lds, grid, lds, s);
   if (enc == kEncW8) return anneal_LE<L, kEncW8>(a, use_lds, grid, lds, s);
   return anneal_LE<L, kEncWide>(a, use_lds, grid, lds, s);
+}
+template <int L, int ENC>
+hipError_t batch_LE(const AnnealArgs &a, int waves, int grid, size_t lds, hipStream_t s) {
+  switch (waves) {
+    case 4: return launch_batch_t<L, ENC, 4>(a, grid, lds, s);
+    case 8: return launch_batch_t<L, ENC, 8>(a, grid, lds, s);
+    case 16: return launch_batch_t<L, ENC, 16>(a, grid, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+template <int L>
+hipError_t batch_L(const AnnealArgs &a, int enc, int waves, int grid, size_t lds, hipStream_t s) {
+  if (enc == kEncPm1) return batch_LE<L, kEncPm1>(a, waves, grid, lds, s);
+  if (enc == kEncW8) return batch_LE<L, kEncW8>(a, waves, grid, lds, s);
+  return batch_LE<L, kEncWide>(a, waves, grid, lds, s);
 }
 template <int L, int ENC>
 hipError_t occ_LE(bool use_lds, size_t lds, int *blocks) {
@@ -637,6 +840,11 @@ hipError_t cut_L(const CutArgs &a, int enc, hipStream_t s) {
 hipError_t launch_anneal(int L, int enc, bool use_lds, const AnnealArgs &a, int grid, size_t lds_bytes,
                          hipStream_t s) {
   ISING_DISPATCH_L(L, anneal_L, a, enc, use_lds, grid, lds_bytes, s);
+}
+
+hipError_t launch_anneal_batch(int L, int enc, int waves, const AnnealArgs &a, int grid, size_t lds_bytes,
+                               hipStream_t s) {
+  ISING_DISPATCH_L(L, batch_L, a, enc, waves, grid, lds_bytes, s);
 }
 
 hipError_t anneal_occupancy(int L, int enc, bool use_lds, size_t lds_bytes, int *blocks_per_cu) {

@@ -16,6 +16,10 @@
 //   kEncWide (otherwise): slot only, plus one int8 weight per entry in a
 //            separate stream, padding = slot 0 with weight 0.
 //
+// Flip draws: one Philox block per (vertex, replica, 4 sweeps).  The sweep
+// that computes a block uses its word for itself and stores the flip bits of
+// the block's later sweeps in three bit planes laid out like the spin state.
+//
 // Spins live as an L-bit mask per slot (bit j = replica j of the group,
 // 1 = +1), L in {1,2,4,8,16,32}; the masks of 32/L consecutive slots share
 // one uint32 word, so the state of n slots is n*L/32 words.  An item with
@@ -32,7 +36,7 @@ constexpr uint32_t kSignBit = 0x80000000u;
 // Chunks of 4 entries each lane prefetches per item; bounds the degree of a
 // row handled with G lanes to 4 * kmax * G (longer rows loop).
 enum Encoding { kEncPm1 = 0, kEncW8 = 1, kEncWide = 2 };
-constexpr int kmax_for(int L, int enc) { return (L >= 32 || enc == kEncWide || (enc == kEncW8 && L >= 2)) ? 2 : 4; }
+constexpr int kmax_for(int L, int enc) { return (L >= 16 || enc == kEncWide || (enc == kEncW8 && L >= 2)) ? 2 : 4; }
 
 // One unit of work for one wavefront.
 struct Item {
@@ -58,6 +62,9 @@ struct AnnealArgs {
   const uint32_t *wave_ptr;  // [n_phases][nw + 1] item ranges per global wavefront
   const uint32_t *cls_w64;   // [n_phases + 1] class boundaries in 64-bit words of the spin state
   uint32_t *spins;           // this replica group's spin words
+  uint32_t *flips;           // 3 planes of n_words: flip bits of sweeps 4b+1..4b+3
+  const uint32_t *own_w64;   // [n_phases][grid][2] 64-bit spin words only this workgroup writes
+  const uint32_t *local;     // [n_phases] 1: the phase runs in workgroup 0 alone
   const uint32_t *thr;       // thresholds, indexed by absolute sweep
   uint32_t *bar;             // barrier words (see kBar*), error flag
   uint32_t n_words;          // spin words of the group
@@ -69,6 +76,10 @@ struct AnnealArgs {
   uint32_t r0;               // replica index of bit 0
   uint32_t r_count;          // replicas of the group in use (<= L)
   uint32_t spin_limit;       // barrier polls before giving up (error flag)
+  // batched launch only
+  const uint32_t *bin_words; // [n_bins + 1] first 32-bit spin word of each bin
+  int32_t n_bins;
+  uint32_t r_total;          // replicas of the handle
 };
 
 struct CutArgs {

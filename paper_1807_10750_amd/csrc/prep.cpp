@@ -137,38 +137,84 @@ int choose_encoding(const HostCSR &g, int64_t n_slots) {
   return n_slots <= ((int64_t)1 << 24) ? kEncW8 : kEncWide;
 }
 
-int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors, int enc, int kmax,
-                 int bin_shift, HostLayout *out, std::string *msg) {
+std::vector<int32_t> pack_components(const HostCSR &g, int64_t target, int32_t *n_bins, int64_t *max_comp) {
+  const int64_t n = g.n;
+  // union-find over the edges
+  std::vector<int32_t> parent(n);
+  for (int64_t v = 0; v < n; ++v) parent[v] = (int32_t)v;
+  auto find = [&](int32_t x) {
+    while (parent[x] != x) {
+      parent[x] = parent[parent[x]];
+      x = parent[x];
+    }
+    return x;
+  };
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t k = g.row_ptr[v]; k < g.row_ptr[v + 1]; ++k) {
+      const int32_t a = find((int32_t)v), b = find(g.col[k]);
+      if (a != b) parent[a < b ? b : a] = a < b ? a : b;
+    }
+  // components in order of their smallest vertex, packed greedily into bins
+  std::vector<int64_t> comp_size(n, 0);
+  for (int64_t v = 0; v < n; ++v) ++comp_size[find((int32_t)v)];
+  std::vector<int32_t> bin_of_root(n, -1), bin(n);
+  int32_t nb = 0;
+  int64_t fill = 0, biggest = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t r = find((int32_t)v);
+    if (bin_of_root[r] < 0) {
+      const int64_t c = comp_size[r];
+      biggest = std::max(biggest, c);
+      if (nb == 0 || fill + c > target) {
+        ++nb;
+        fill = 0;
+      }
+      bin_of_root[r] = nb - 1;
+      fill += c;
+    }
+    bin[v] = bin_of_root[r];
+  }
+  *n_bins = nb;
+  *max_comp = biggest;
+  return bin;
+}
+
+int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors, const int32_t *bin_of,
+                 int32_t n_bins, int enc, int kmax, int bin_shift, HostLayout *out, std::string *msg) {
   HostLayout &L = *out;
   const int64_t n = g.n;
   const int64_t *rp = g.row_ptr;
   try {
     L.enc = enc;
     L.n_phases = n_colors;
+    L.n_bins = std::max(1, n_bins);
+    // classes are (bin, colour) pairs: key = bin * n_colors + colour
+    const int64_t n_cls = (int64_t)L.n_bins * n_colors;
+    auto key = [&](int64_t v) { return (bin_of ? (int64_t)bin_of[v] * n_colors : 0) + color[v]; };
     // vertices of each class, by (degree desc, id asc)
-    std::vector<int64_t> cnt(n_colors + 1, 0);
-    for (int64_t v = 0; v < n; ++v) ++cnt[color[v] + 1];
-    for (int32_t c = 0; c < n_colors; ++c) cnt[c + 1] += cnt[c];
+    std::vector<int64_t> cnt(n_cls + 1, 0);
+    for (int64_t v = 0; v < n; ++v) ++cnt[key(v) + 1];
+    for (int64_t c = 0; c < n_cls; ++c) cnt[c + 1] += cnt[c];
     std::vector<int32_t> byc(n);
     {
       std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-      for (int64_t v = 0; v < n; ++v) byc[fill[color[v]]++] = (int32_t)v;
+      for (int64_t v = 0; v < n; ++v) byc[fill[key(v)]++] = (int32_t)v;
     }
     auto deg = [&](int32_t v) { return rp[v + 1] - rp[v]; };
-    for (int32_t c = 0; c < n_colors; ++c)
+    for (int64_t c = 0; c < n_cls; ++c)
       std::stable_sort(byc.begin() + cnt[c], byc.begin() + cnt[c + 1],
                        [&](int32_t a, int32_t b) { return deg(a) > deg(b); });
     // slots: each class padded to a multiple of 64
-    L.cls_begin.assign(n_colors + 1, 0);
-    for (int32_t c = 0; c < n_colors; ++c) {
+    L.cls_begin.assign(n_cls + 1, 0);
+    for (int64_t c = 0; c < n_cls; ++c) {
       const int64_t size = cnt[c + 1] - cnt[c];
       L.cls_begin[c + 1] = L.cls_begin[c] + (size + 63) / 64 * 64;
     }
-    L.n_slots = L.cls_begin[n_colors];
+    L.n_slots = L.cls_begin[n_cls];
     if (L.n_slots >= (int64_t)0x7FFFFFFF) { *msg = "too many vertices"; return kPrepArg; }
     L.vid.assign(L.n_slots, -1);
     L.slot_of.assign(n, -1);
-    for (int32_t c = 0; c < n_colors; ++c)
+    for (int64_t c = 0; c < n_cls; ++c)
       for (int64_t i = cnt[c]; i < cnt[c + 1]; ++i) {
         const int64_t slot = L.cls_begin[c] + (i - cnt[c]);
         L.vid[slot] = byc[i];
@@ -179,14 +225,14 @@ int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_
     // {1, 4, 16, 64} whose prefetch depth covers the first (largest) row's
     // degree, widened until K = 64 / G divides pos; it spans K rows.
     L.items.clear();
-    L.phase_items.assign(n_colors + 1, 0);
+    L.phase_items.assign(n_cls + 1, 0);
     uint64_t chunks = 0;  // uint4 chunks allocated so far
     auto lanes_for = [&](int64_t d) -> uint32_t {
       for (uint32_t lanes = 1; lanes < 64; lanes *= 4)
         if (d <= ((4 * (int64_t)kmax * (int64_t)lanes) >> bin_shift)) return lanes;
       return 64;
     };
-    for (int32_t c = 0; c < n_colors; ++c) {
+    for (int64_t c = 0; c < n_cls; ++c) {
       const int64_t size = cnt[c + 1] - cnt[c];
       for (int64_t pos = 0; pos < size;) {
         const int32_t first = L.vid[L.cls_begin[c] + pos];
@@ -258,28 +304,57 @@ std::vector<int32_t> phase_classes(const HostLayout &L, const std::vector<int64_
   return out;
 }
 
-std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int32_t> &phase_cls, int32_t nw) {
+std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int32_t> &phase_cls, int32_t nw,
+                                      const std::vector<uint32_t> &local, int32_t local_waves) {
   const int32_t n_ph = (int32_t)phase_cls.size() - 1;
   std::vector<uint32_t> out((size_t)n_ph * (nw + 1));
   for (int32_t p = 0; p < n_ph; ++p) {
     const uint32_t b = L.phase_items[phase_cls[p]], e = L.phase_items[phase_cls[p + 1]];
+    const int32_t nwp = local[p] ? std::min(local_waves, nw) : nw;  // waves that share the phase
     std::vector<uint64_t> prefix(e - b + 1, 0);
     for (uint32_t i = b; i < e; ++i) {
       const Item &it = L.items[i];
-      const uint64_t cost = 64 + (uint64_t)it.len4 * 4 * (64 / it.g);
+      // a fixed share for the item's latency chain plus its entries
+      const uint64_t cost = 512 + (uint64_t)it.len4 * 4 * (64 / it.g);
       prefix[i - b + 1] = prefix[i - b] + cost;
     }
     const uint64_t total = prefix.back();
     uint32_t *o = &out[(size_t)p * (nw + 1)];
     uint32_t j = 0;
     for (int32_t w = 0; w <= nw; ++w) {
-      // first item whose cost prefix reaches w/nw of the phase
+      if (w >= nwp) {
+        o[w] = e;
+        continue;
+      }
+      // first item whose cost prefix reaches w/nwp of the phase
       const unsigned __int128 goal = (unsigned __int128)total * (uint64_t)w;
-      while (j < e - b && (unsigned __int128)prefix[j] * (uint64_t)nw < goal) ++j;
+      while (j < e - b && (unsigned __int128)prefix[j] * (uint64_t)nwp < goal) ++j;
       o[w] = b + j;
     }
     o[nw] = e;
   }
+  return out;
+}
+
+std::vector<uint32_t> own_words(const HostLayout &L, const std::vector<uint32_t> &wave_ptr, int32_t n_ph,
+                                int32_t grid, int32_t waves_per_block, int Lbits) {
+  std::vector<uint32_t> out((size_t)n_ph * grid * 2, 0);
+  const int32_t nw = grid * waves_per_block;
+  for (int32_t p = 0; p < n_ph; ++p)
+    for (int32_t g = 0; g < grid; ++g) {
+      const uint32_t i0 = wave_ptr[(size_t)p * (nw + 1) + (size_t)g * waves_per_block];
+      const uint32_t i1 = wave_ptr[(size_t)p * (nw + 1) + (size_t)(g + 1) * waves_per_block];
+      uint32_t *o = &out[((size_t)p * grid + g) * 2];
+      if (i0 >= i1) continue;
+      const Item &f = L.items[i0], &l = L.items[i1 - 1];
+      const uint64_t bit_lo = (uint64_t)f.id * Lbits;
+      const uint64_t bit_hi = ((uint64_t)l.id + 64 / l.g) * Lbits;
+      const uint64_t lo = (bit_lo + 63) / 64, hi = bit_hi / 64;
+      if (lo < hi) {
+        o[0] = (uint32_t)lo;
+        o[1] = (uint32_t)hi;
+      }
+    }
   return out;
 }
 
@@ -305,7 +380,7 @@ bool check_layout(const HostLayout &L, std::string *msg) {
       return false;
     }
   }
-  for (int32_t p = 0; p < L.n_phases; ++p)
+  for (int64_t p = 0; p < (int64_t)L.n_bins * L.n_phases; ++p)
     if (L.cls_begin[p] % 64 != 0 || L.phase_items[p] > L.phase_items[p + 1]) {
       *msg = "layout class table inconsistent";
       return false;

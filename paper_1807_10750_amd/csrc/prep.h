@@ -41,24 +41,32 @@ int32_t greedy_coloring(const HostCSR &g, bool largest_first, std::vector<int32_
 
 struct HostLayout {
   int64_t n_slots = 0;                 // multiple of 64
-  int32_t n_phases = 0;                // colour classes
+  int32_t n_phases = 0;                // colours
+  int32_t n_bins = 1;                  // groups of whole components laid out one after another
   int enc = 0;                         // Encoding of the entries
   std::vector<int32_t> vid;            // slot -> vertex (-1 = padding)
   std::vector<int32_t> slot_of;        // vertex -> slot
-  std::vector<int64_t> cls_begin;      // [n_phases + 1] first slot of each class
+  std::vector<int64_t> cls_begin;      // [n_bins * n_phases + 1] first slot of class (bin, colour)
   std::vector<uint32_t> entries;       // edge stream, multiple of 4 entries
   std::vector<int8_t> wts;             // per entry (general weights only)
   std::vector<Item> items;             // phase by phase
-  std::vector<uint32_t> phase_items;   // [n_phases + 1]
+  std::vector<uint32_t> phase_items;   // [n_bins * n_phases + 1] first item of class (bin, colour)
 };
 
 // The entry encoding a graph with n_slots slots gets.
 int choose_encoding(const HostCSR &g, int64_t n_slots);
 
-// enc: entry encoding; kmax: chunks each lane prefetches (see kmax_for); a
-// row of degree d gets the fewest lanes G with d <= (4 * kmax * G) >> bin_shift.
-int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors, int enc, int kmax,
-                 int bin_shift, HostLayout *out, std::string *msg);
+// Connected components (union-find), packed in order of their smallest
+// vertex into bins of at most target vertices (a larger component gets a bin
+// of its own).  Returns the bin of every vertex; *max_comp = largest component.
+std::vector<int32_t> pack_components(const HostCSR &g, int64_t target, int32_t *n_bins, int64_t *max_comp);
+
+// Classes are (bin, colour) pairs, laid out bin by bin (bin_of = NULL: one
+// bin).  enc: entry encoding; kmax: chunks each lane prefetches (see
+// kmax_for); a row of degree d gets the fewest lanes G with
+// d <= (4 * kmax * G) >> bin_shift.
+int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors, const int32_t *bin_of,
+                 int32_t n_bins, int enc, int kmax, int bin_shift, HostLayout *out, std::string *msg);
 
 // Phases of a sweep as runs of consecutive colour classes: [cls[i], cls[i+1]).
 // Deterministic mode uses one class per phase.  Async mode keeps every class
@@ -68,8 +76,16 @@ int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_
 std::vector<int32_t> phase_classes(const HostLayout &L, const std::vector<int64_t> &class_size, int merge_div);
 
 // Splits each phase's items over nw wavefronts in contiguous runs of about
-// equal cost.  Returns [n_phases][nw + 1] item offsets.
-std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int32_t> &phase_cls, int32_t nw);
+// equal cost; a phase with local[p] != 0 goes to the first local_waves
+// wavefronts (one workgroup) only.  Returns [n_phases][nw + 1] item offsets.
+std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int32_t> &phase_cls, int32_t nw,
+                                      const std::vector<uint32_t> &local, int32_t local_waves);
+
+// For each phase and workgroup (waves_per_block consecutive wavefronts), the
+// 64-bit spin words written by that workgroup alone: [lo, hi), or [0, 0).
+// Words shared with a neighbouring workgroup's items are left out.
+std::vector<uint32_t> own_words(const HostLayout &L, const std::vector<uint32_t> &wave_ptr, int32_t n_ph,
+                                int32_t grid, int32_t waves_per_block, int Lbits);
 
 // Verifies that every item addresses only memory inside the layout (index
 // ranges of entries, slots and spin words).  Returns false with a message.

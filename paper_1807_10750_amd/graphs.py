@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "CSRGraph", "from_edges", "empty", "path", "cycle", "complete",
     "complete_bipartite", "star", "torus", "erdos_renyi", "powerlaw_chung_lu",
-    "random_regular", "batched_erdos_renyi", "random_spins", "relabel",
+    "random_regular", "batched_erdos_renyi", "random_spins", "relabel", "disjoint_union",
 ]
 
 
@@ -307,3 +307,19 @@ def relabel(g: CSRGraph, perm: np.ndarray) -> CSRGraph:
     u, v, w = g.edges()
     pu, pv = perm[u], perm[v]
     return from_edges(g.n, np.minimum(pu, pv), np.maximum(pu, pv), w, g.name + "_relabel")
+
+
+def disjoint_union(graphs, name: str = "") -> CSRGraph:
+    """Block-diagonal union: graph i's vertex v becomes offset_i + v."""
+    n = sum(g.n for g in graphs)
+    us, vs, ws = [], [], []
+    off = 0
+    for g in graphs:
+        u, v, w = g.edges()
+        us.append(u + off)
+        vs.append(v + off)
+        ws.append(w)
+        off += g.n
+    cat = (lambda xs, dt: np.concatenate(xs) if xs else np.zeros(0, dt))
+    return from_edges(n, cat(us, np.int64), cat(vs, np.int64), cat(ws, np.int8),
+                      name or f"union{len(graphs)}")

@@ -1,0 +1,122 @@
+"""Batched mode: a graph made of many small components (a batch of graphs,
+the paper's many independent G-set-sized instances) runs one workgroup per bin
+of whole components.  Results must equal the oracle's anneal of the union
+graph bit for bit in deterministic mode; async is judged by cut statistics.
+"""
+import contextlib
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1807_10750_amd import graphs as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def I():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_10750_amd import ising
+    return ising
+
+
+@contextlib.contextmanager
+def env(**kw):
+    old = {k: os.environ.get(k) for k in kw}
+    try:
+        for k, v in kw.items():
+            os.environ[k] = str(v)
+        yield
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def run_both(I, g, seed, M, R, lf=False, mode=0, t_begin=0, t_end=None):
+    gr = I.Graph.from_csr(g, coloring=int(lf), replicas=R)
+    gr.randomize(seed)
+    sch = I.make_schedule(0.1, 0.0, M)
+    gr.anneal(sch, seed, mode, t_begin, M if t_end is None else t_end)
+    sg = gr.spins()
+    Cg, Eg = gr.cut()
+    info = gr.info()
+    gr.close()
+    col, nc = O.color(g, lf)
+    so = O.anneal(g, O.order(col, nc), O.init_spins(g.n, R, seed), O.thresholds(0.1, 0.0, M), seed,
+                  t_begin, M if t_end is None else t_end)
+    return sg, Cg, Eg, so, info
+
+
+def small_batch(count, seed, n_lo=64, n_hi=600):
+    return G.disjoint_union(G.batched_erdos_renyi(count, n_lo, n_hi, 3.0, 20.0, "pm1", seed))
+
+
+@pytest.mark.parametrize("R", [1, 3, 8, 16])
+def test_batched_union_bit_exact(I, R):
+    g = small_batch(40, 3)
+    sg, Cg, Eg, so, info = run_both(I, g, 5, 60, R)
+    assert info["bins"] >= 2, info
+    assert np.array_equal(sg, so)
+    C, E = O.cut(g, so)
+    assert np.array_equal(Cg, C) and np.array_equal(Eg, E)
+
+
+@pytest.mark.parametrize("knobs", [dict(ISING_BIN_VERTICES=64), dict(ISING_BIN_VERTICES=1000),
+                                   dict(ISING_BATCH_WAVES=8), dict(ISING_BATCH_WAVES=16),
+                                   dict(ISING_BIN_SHIFT=4)])
+def test_batched_launch_shapes_bit_exact(I, knobs):
+    g = small_batch(30, 4)
+    with env(**knobs):
+        sg, Cg, Eg, so, info = run_both(I, g, 6, 40, 4, lf=True, t_begin=3, t_end=33)
+    assert info["bins"] >= 2
+    assert np.array_equal(sg, so)
+
+
+def test_mixed_weights_and_isolated_components(I):
+    parts = [G.erdos_renyi(200, 0.05, "int8", 1), G.empty(300), G.torus(10, 12), G.star(50, weights=-128),
+             G.random_regular(400, 3, "pm1", 2), G.cycle(9)]
+    g = G.disjoint_union(parts)
+    with env(ISING_BIN_VERTICES=256):
+        sg, Cg, Eg, so, info = run_both(I, g, 7, 50, 5)
+    assert info["bins"] >= 2
+    assert np.array_equal(sg, so)
+
+
+def test_large_component_falls_back_to_one_launch(I):
+    g = G.disjoint_union([G.torus(150, 150), G.cycle(10)])  # 22 500-vertex component
+    sg, Cg, Eg, so, info = run_both(I, g, 8, 20, 2)
+    assert info["bins"] == 0
+    assert np.array_equal(sg, so)
+
+
+def test_config4_shape_sample(I):
+    # 128 ER graphs with n ~ U{64..4096}, mean degree ~ U[3, 20], +-1, 8 replicas
+    g = G.disjoint_union(G.batched_erdos_renyi(128, 64, 4096, 3.0, 20.0, "pm1", 11))
+    sg, Cg, Eg, so, info = run_both(I, g, 9, 100, 8, t_begin=0, t_end=100)
+    assert info["bins"] >= 2 and info["replicas_per_group"] == 8
+    assert np.array_equal(sg, so)
+
+
+def test_batched_async_statistics(I):
+    g = G.disjoint_union([G.random_regular(2000, 3, "one", s) for s in range(8)])
+    R, M = 16, 300
+    gr = I.Graph.from_csr(g, replicas=R)
+    gr.randomize(1)
+    gr.anneal(I.make_schedule(0.1, 0.0, M), 1, I.MODE_ASYNC)
+    a = gr.cut()[0].astype(float)
+    gr.close()
+    col, nc = O.color(g)
+    o = []
+    for sd in range(16):
+        s = O.anneal(g, O.order(col, nc), O.init_spins(g.n, 1, 100 + sd), O.thresholds(0.1, 0.0, M), 100 + sd, 0, M)
+        o.append(O.cut(g, s)[0][0])
+    o = np.array(o, float)
+    se = np.sqrt(a.var(ddof=1) / len(a) + o.var(ddof=1) / len(o))
+    assert a.mean() >= o.mean() - max(3 * se, 0.005 * o.mean())

@@ -35,7 +35,13 @@ WORKLOADS = {
                      sweeps=5000, replicas=16),
     "er800": dict(desc="Erdos-Renyi n=800 p=0.06, w +1, 1000 sweeps, 16 seeds as replicas",
                   sweeps=1000, replicas=16),
+    "batch4096": dict(desc="4096 Erdos-Renyi graphs, n ~ U{64..4096}, mean degree ~ U[3,20], w +-1, "
+                           "8 replicas each, 1000 sweeps, one batched launch",
+                      sweeps=1000, replicas=8),
 }
+
+KERNEL_SOURCES = ["paper_1807_10750_amd/csrc/kernels.hip", "paper_1807_10750_amd/csrc/prep.cpp",
+                  "paper_1807_10750_amd/csrc/api.cpp", "paper_1807_10750_amd/csrc/layout.h"]
 
 
 def make_graph(name):
@@ -46,7 +52,44 @@ def make_graph(name):
         return G.torus(200, 200, weights="pm1", seed=1)
     if name == "er800":
         return G.erdos_renyi(800, 0.06, "one", 1)
+    if name == "batch4096":
+        return G.disjoint_union(G.batched_erdos_renyi(4096, 64, 4096, 3.0, 20.0, "pm1", 1))
     raise ValueError(name)
+
+
+def sources_digest():
+    """SHA-256 over the sources that decide what the anneal kernel reads and writes."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(path, workload, mode):
+    """HBM bytes per anneal launch from a committed rocprofv3 counter summary.
+
+    The summary records FETCH_SIZE and WRITE_SIZE of k_anneal (KiB per
+    dispatch), the copy-probe scale factors and the digest of the kernel
+    sources it was taken on.  Returns None when there is no summary for this
+    workload and mode or the sources have changed since.
+    """
+    if not path or not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("workload") != workload or fields.get("mode") != mode:
+        return None
+    if fields.get("sources_sha256") != sources_digest():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def algorithmic_bytes_per_sweep(g, info):
@@ -99,7 +142,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=None, help="override the schedule length")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--p-start", type=float, default=0.1, help="initial flip probability of the linear schedule")
-    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per anneal launch")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_anneal_traffic_powerlaw1m_async.txt"),
+                    help="rocprofv3 counter summary giving HBM bytes per anneal launch")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -181,9 +225,7 @@ def main():
     moved = moved_bytes_per_sweep(info) * info["n_groups"] * M
     mean_anneal_s = float(np.mean(anneal_ms)) / 1e3
     achieved = alg / mean_anneal_s / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get(args.workload)
+    traffic = measured_traffic(args.traffic, args.workload, args.mode) if M == wl["sweeps"] else None
     out = {
         "metric": "spin-updates/sec",
         "value": value,
@@ -208,6 +250,7 @@ def main():
                      "anneal_ms_min": float(np.min(anneal_ms)),
                      "algorithmic_bytes_per_launch": alg, "moved_bytes_per_launch": moved},
         "final_cut_last_step": int(cuts[0]),
+        "sources_sha256": sources_digest(),
         "create_s": create_s,
     }
     if args.cpu_budget > 0:

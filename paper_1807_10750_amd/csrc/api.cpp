@@ -302,7 +302,8 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
     } catch (const std::bad_alloc &) {
       return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed while finding components"));
     }
-    g->batch = n_bins >= 2 && max_comp <= 16384;
+    // a batch of small graphs, or one small graph whose replicas spread over workgroups
+    g->batch = max_comp <= 16384 && (n_bins >= 2 || n_replicas >= 2);
     if (g->batch) {
       std::vector<int64_t> cnt((size_t)n_bins * g->n_colors, 0);
       for (int64_t v = 0; v < n; ++v) ++cnt[(size_t)bin_of[v] * g->n_colors + g->color[v]];
@@ -323,6 +324,8 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   for (int64_t v = 0; v < n; ++v) ++class_size[g->color[v]];
   for (int64_t c : class_size) n_slots += (c + 63) / 64 * 64;
   int L = pow2_at_least(n_replicas);
+  // one small graph: one replica per workgroup, so replicas run in parallel
+  if (g->batch && n_bins == 1) L = (int)std::min<int64_t>(L, std::max<int64_t>(1, env_int("ISING_BATCH_L", 1)));
   const size_t budget = g->batch ? (size_t)64 * 1024 : kLdsBudget;
   const int64_t lds_slots = g->batch ? max_bin_slots : n_slots;
   auto state_bytes = [&](int l) { return (size_t)lds_slots * (size_t)l / 8; };

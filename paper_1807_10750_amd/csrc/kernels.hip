@@ -384,8 +384,10 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   const bool multi = gridDim.x > 1;
   const bool fenced = !USE_LDS;
   const uint32_t n_grp = gridDim.x < 8u ? gridDim.x : 8u;
-  // two items in flight where the registers allow it
-  constexpr bool kDeep = ENC == kEncPm1 && L <= 8;
+  // Pipeline shape that fits the registers: two items in flight (three
+  // buffers), one item in flight unrolled, or one item in flight rolled.
+  constexpr bool kDeep = ENC == kEncPm1 && L <= 4;
+  constexpr bool kUnrolled = L <= 4;
   if (USE_LDS) {
     restage(a, lds, 0, a.n_words / 2, threadIdx.x, blockDim.x);
     __syncthreads();
@@ -407,27 +409,53 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
     const int plane = plane_of(t);
     for (int32_t ph = 0; ph < a.n_phases; ++ph) {
+      // Items of this phase.  On entry fa holds the loads of item ib.  The
+      // loop is unrolled by the pipeline depth so the buffers change roles
+      // without register copies (a copy would wait for its loads).
       if (kDeep) {
-        // items of this phase, two ahead in flight
-        Item itb;
+        // two items ahead: fa, fb, fc in rotation
+        Item itb, itc;
         if (ib + 1 < ie) {
           itb = a.items[ib + 1];
           fetch<L, ENC>(a, itb, lane, fb, plane);
         }
-        for (uint32_t i = ib; i < ie; ++i) {
-          Item itc;
+        for (uint32_t i = ib; i < ie; i += 3) {
           if (i + 2 < ie) {
             itc = a.items[i + 2];
             fetch<L, ENC>(a, itc, lane, fc, plane);
           }
           compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
-          ita = itb;
-          fa = fb;
-          itb = itc;
-          fb = fc;
+          if (i + 1 >= ie) break;
+          if (i + 3 < ie) {
+            ita = a.items[i + 3];
+            fetch<L, ENC>(a, ita, lane, fa, plane);
+          }
+          compute<L, ENC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0);
+          if (i + 2 >= ie) break;
+          if (i + 4 < ie) {
+            itb = a.items[i + 4];
+            fetch<L, ENC>(a, itb, lane, fb, plane);
+          }
+          compute<L, ENC, USE_LDS>(a, itc, lane, fc, lds, (uint32_t)t, plane < 0);
+        }
+      } else if (kUnrolled) {
+        // one item ahead: fa, fb in rotation
+        Item itb;
+        for (uint32_t i = ib; i < ie; i += 2) {
+          if (i + 1 < ie) {
+            itb = a.items[i + 1];
+            fetch<L, ENC>(a, itb, lane, fb, plane);
+          }
+          compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
+          if (i + 1 >= ie) break;
+          if (i + 2 < ie) {
+            ita = a.items[i + 2];
+            fetch<L, ENC>(a, ita, lane, fa, plane);
+          }
+          compute<L, ENC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0);
         }
       } else {
-        // items of this phase, one ahead in flight
+        // one item ahead, rolled: the copy waits for the next item's loads
         for (uint32_t i = ib; i < ie; ++i) {
           const bool more = i + 1 < ie;
           Item itb;
@@ -557,18 +585,20 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
     const int plane = plane_of(t);
     for (int32_t ph = 0; ph < a.n_phases; ++ph) {
-      for (uint32_t i = ib; i < ie; ++i) {
-        const bool more = i + 1 < ie;
-        Item itb;
-        if (more) {
+      // one item ahead, unrolled so fa and fb swap roles without copies
+      Item itb;
+      for (uint32_t i = ib; i < ie; i += 2) {
+        if (i + 1 < ie) {
           itb = a.items[i + 1];
           fetch<L, ENC>(a, itb, lane, fb, plane);
         }
         compute<L, ENC, true>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, w0);
-        if (more) {
-          ita = itb;
-          fa = fb;
+        if (i + 1 >= ie) break;
+        if (i + 2 < ie) {
+          ita = a.items[i + 2];
+          fetch<L, ENC>(a, ita, lane, fa, plane);
         }
+        compute<L, ENC, true>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, w0);
       }
       const bool last_phase = ph + 1 == a.n_phases;
       const int32_t nph = last_phase ? 0 : ph + 1;

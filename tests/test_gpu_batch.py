@@ -120,3 +120,13 @@ def test_batched_async_statistics(I):
     o = np.array(o, float)
     se = np.sqrt(a.var(ddof=1) / len(a) + o.var(ddof=1) / len(o))
     assert a.mean() >= o.mean() - max(3 * se, 0.005 * o.mean())
+
+
+@pytest.mark.parametrize("knobs", [dict(), dict(ISING_BATCH_L=4), dict(ISING_BATCH_L=16, ISING_BATCH_WAVES=8)])
+def test_single_small_graph_spreads_replicas(I, knobs):
+    # config 1's shape: one 800-vertex ER graph, 16 seeds as replicas
+    g = G.erdos_renyi(800, 0.06, "one", 1)
+    with env(**knobs):
+        sg, Cg, Eg, so, info = run_both(I, g, 0, 200, 16)
+    assert info["bins"] == 1 and info["n_groups"] == 16 // info["replicas_per_group"]
+    assert np.array_equal(sg, so)

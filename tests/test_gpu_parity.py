@@ -120,9 +120,12 @@ def test_small_graphs_bit_exact(I, name, make, R):
 
 
 @pytest.mark.parametrize("R", [2, 16, 33])
-def test_replica_packing_bit_exact(I, R):
+@pytest.mark.parametrize("batch", [True, False])
+def test_replica_packing_bit_exact(I, R, batch):
     g = G.erdos_renyi(500, 0.02, "pm1", 9)
-    assert_same(I, g, seed=5, ps=0.15, pe=0.0, M=30, R=R)
+    with env(ISING_NO_BATCH=0 if batch else 1):
+        info = assert_same(I, g, seed=5, ps=0.15, pe=0.0, M=30, R=R)
+    assert (info["bins"] > 0) == batch
 
 
 @pytest.mark.parametrize("lf", [False, True])
@@ -181,12 +184,14 @@ KNOBS = [dict(ISING_GRID=1), dict(ISING_GRID=3), dict(ISING_GRID=64), dict(ISING
 @pytest.mark.parametrize("knobs", KNOBS)
 @pytest.mark.parametrize("weights", ["pm1", "int8"])
 def test_launch_configuration_invariance(I, knobs, weights):
+    # one cooperative launch (batching off) in every launch shape
     g = G.powerlaw_chung_lu(6000, max_deg=500, weights=weights, seed=12)
-    with env(**knobs):
-        assert_same(I, g, seed=13, ps=0.2, pe=0.0, M=25, R=3)
+    with env(ISING_NO_BATCH=1, **knobs):
+        info = assert_same(I, g, seed=13, ps=0.2, pe=0.0, M=25, R=3)
+    assert info["bins"] == 0
 
 
-@pytest.mark.parametrize("knobs", [dict(ISING_WIDE=1), dict(ISING_WIDE=1, ISING_GRID=4),
+@pytest.mark.parametrize("knobs", [dict(ISING_WIDE=1), dict(ISING_WIDE=1, ISING_GRID=4, ISING_NO_BATCH=1),
                                    dict(ISING_WIDE=1, ISING_NO_LDS=1, ISING_BIN_SHIFT=3)])
 @pytest.mark.parametrize("R", [1, 5, 16])
 def test_wide_weight_stream(I, knobs, R):

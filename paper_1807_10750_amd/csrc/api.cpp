@@ -34,7 +34,6 @@ ising_status_t hip_fail(hipError_t e, const char *what) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
-constexpr size_t kLdsBudget = 160 * 1024 - 2048;  // gfx950 LDS per workgroup, minus static use
 
 bool is_device_ptr(const void *p) {
   if (p == nullptr) return false;

@@ -10,6 +10,9 @@
 namespace ising {
 
 constexpr int kAnnealBlock = 1024;  // 16 wavefronts per workgroup
+// Largest spin state the cooperative anneal mirrors in LDS (a static array
+// of the kernel: its address is a compile-time constant).
+constexpr size_t kLdsBudget = 160 * 1024 - 2048;
 
 hipError_t launch_anneal(int L, int enc, bool use_lds, const AnnealArgs &a, int grid, size_t lds_bytes,
                          hipStream_t s);

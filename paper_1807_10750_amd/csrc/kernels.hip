@@ -80,37 +80,44 @@ __device__ __forceinline__ uint32_t mask_of(P words, uint32_t s, uint32_t woff =
   return (words[(bit >> 5) - woff] >> (bit & 31)) & lmask<L>();
 }
 
-// Adds the contribution of one edge entry to the L field accumulators
-// (entry encodings: see layout.h; wv is the separate weight of kEncWide).
+// Per-entry field accumulation.  With +-1 weights, c[j] counts the entries
+// whose neighbour bit (replica j) differs from the entry's sign bit; the
+// field is then 2 c[j] - (entries of the row).  With general weights, c[j]
+// sums the weights of the entries whose neighbour bit is set and sw sums all
+// weights; the field is 2 c[j] - sw.  Padding entries (layout.h) keep both
+// forms exact without a test per entry.
 template <int L, int ENC, typename P>
-__device__ __forceinline__ void accumulate(int32_t (&h)[L], uint32_t x, int32_t wv, P words, uint32_t woff) {
+__device__ __forceinline__ void accumulate(int32_t (&c)[L], int32_t &sw, uint32_t x, int32_t wv, P words,
+                                           uint32_t woff) {
+  const uint32_t slot = ENC == kEncPm1 ? (x & ~kSignBit) : (ENC == kEncW8 ? (x & 0xFFFFFFu) : x);
+  const uint32_t word = words[((slot * L) >> 5) - woff];
+  // bits [4:0] of the offset operand select the bit; for L = 1 those are slot bits [4:0]
+  const uint32_t m = L == 1 ? word : word >> ((slot * L) & 31u);
+  const uint32_t off0 = L == 1 ? x : 0u;
   if (ENC == kEncPm1) {
-    const bool valid = x != kSentinel;
-    const uint32_t slot = valid ? (x & ~kSignBit) : 0u;
-    uint32_t m = mask_of<L>(words, slot, woff);
-    if (x & kSignBit) m = ~m;
+    const uint32_t neg = x >> 31;
 #pragma unroll
-    for (int j = 0; j < L; ++j) h[j] += valid ? (int32_t)(((m >> j) & 1u) << 1) - 1 : 0;
+    for (int j = 0; j < L; ++j) c[j] += (int32_t)(__builtin_amdgcn_ubfe(m, off0 + (uint32_t)j, 1u) ^ neg);
   } else {
-    const uint32_t slot = ENC == kEncW8 ? (x & 0xFFFFFFu) : x;
     const int32_t w = ENC == kEncW8 ? (int32_t)(int8_t)(x >> 24) : wv;
-    const uint32_t m = mask_of<L>(words, slot, woff);
 #pragma unroll
-    for (int j = 0; j < L; ++j) h[j] += ((m >> j) & 1u) ? w : -w;
+    for (int j = 0; j < L; ++j) c[j] += (int32_t)__builtin_amdgcn_ubfe(m, off0 + (uint32_t)j, 1u) * w;
+    sw += w;
   }
 }
 
 template <int L, int ENC, typename P>
-__device__ __forceinline__ void accumulate4(int32_t (&h)[L], const uint4 &x, uint32_t wv, P words, uint32_t woff) {
-  accumulate<L, ENC>(h, x.x, (int32_t)(int8_t)(wv), words, woff);
-  accumulate<L, ENC>(h, x.y, (int32_t)(int8_t)(wv >> 8), words, woff);
-  accumulate<L, ENC>(h, x.z, (int32_t)(int8_t)(wv >> 16), words, woff);
-  accumulate<L, ENC>(h, x.w, (int32_t)(int8_t)(wv >> 24), words, woff);
+__device__ __forceinline__ void accumulate4(int32_t (&c)[L], int32_t &sw, const uint4 &x, uint32_t wv, P words,
+                                            uint32_t woff) {
+  accumulate<L, ENC>(c, sw, x.x, (int32_t)(int8_t)(wv), words, woff);
+  accumulate<L, ENC>(c, sw, x.y, (int32_t)(int8_t)(wv >> 8), words, woff);
+  accumulate<L, ENC>(c, sw, x.z, (int32_t)(int8_t)(wv >> 16), words, woff);
+  accumulate<L, ENC>(c, sw, x.w, (int32_t)(int8_t)(wv >> 24), words, woff);
 }
 
 // Local update (Eq. 2 with J = -w, a zero field keeps the spin) of every
 // replica bit, then the annealing flips (bit j set = flip replica j).
-// Padding slots have no edges and draw no flips; their bits are never read.
+// Padding slots have only padding entries (whose pairs cancel) and draw no flips.
 template <int L>
 __device__ __forceinline__ uint32_t update_mask(const int32_t (&h)[L], uint32_t own, uint32_t flips) {
   uint32_t nm = 0;
@@ -185,8 +192,9 @@ __device__ __forceinline__ void bar_arrive(uint32_t *bar, bool fenced) {
   }
 }
 
-__device__ __forceinline__ bool bar_wait(uint32_t *bar, uint32_t target, uint32_t limit, bool fenced) {
-  __shared__ uint32_t s_ok;
+// s_ok: one LDS word of the workgroup that carries the verdict to every thread.
+__device__ __forceinline__ bool bar_wait(uint32_t *bar, uint32_t target, uint32_t limit, bool fenced,
+                                         uint32_t &s_ok) {
   if (threadIdx.x == 0) {
     uint32_t ok = 1, polls = 0;
     while (__hip_atomic_load(bar + kBarTop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -224,22 +232,24 @@ struct Fetched {
 template <int L, int ENC>
 __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it, int lane, Fetched<L, ENC> &f, int plane) {
   constexpr int KM = Fetched<L, ENC>::KM;
-  const uint32_t G = it.g, K = 64u / G;
-  const uint32_t r = (uint32_t)lane / G, gl = (uint32_t)lane & (G - 1u);
+  const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs, K = 64u >> gs;
+  const uint32_t r = (uint32_t)lane >> gs, gl = (uint32_t)lane & (G - 1u);
   const uint32_t slot = it.id + r;
   f.vid = plane < 0 ? a.vid[slot] : 0;  // the caller id only keys the Philox draws
   f.ownw = ld_coherent(a.spins + ((slot * L) >> 5));
   f.flipw = plane >= 0 ? ld_coherent(a.flips + (size_t)plane * a.n_words + ((slot * L) >> 5)) : 0u;
+  // the item's block starts at a wave-uniform address; offsets inside it fit 32 bits
+  const uint4 *blk = a.entries + it.base4;
+  const uint32_t *wblk = ENC == kEncWide ? a.wts4 + it.base4 : nullptr;
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
     const uint32_t q = gl + (uint32_t)k * G;
     if (q < it.len4) {
-      const size_t idx = (size_t)it.base4 + (size_t)q * K + r;
-      f.e[k] = a.entries[idx];
-      if (ENC == kEncWide) f.w[k < Fetched<L, ENC>::KW ? k : 0] = a.wts4[idx];
-    } else {
-      f.e[k] = ENC == kEncPm1 ? make_uint4(kSentinel, kSentinel, kSentinel, kSentinel) : make_uint4(0, 0, 0, 0);
-      if (ENC == kEncWide) f.w[k < Fetched<L, ENC>::KW ? k : 0] = 0u;
+      const uint32_t idx = (q << ks) + r;
+      f.e[k] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + idx * 16u);
+      if (ENC == kEncWide)
+        f.w[k < Fetched<L, ENC>::KW ? k : 0] =
+            *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(wblk) + idx * 4u);
     }
   }
 }
@@ -251,10 +261,10 @@ template <int L, int ENC, bool USE_LDS>
 __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it, int lane, const Fetched<L, ENC> &f,
                                         uint32_t *lds, uint32_t t, bool draws, uint32_t woff = 0) {
   constexpr int KM = Fetched<L, ENC>::KM;
-  const uint32_t G = it.g, K = 64u / G;
-  const uint32_t r = (uint32_t)lane / G, gl = (uint32_t)lane & (G - 1u);
+  const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs, K = 64u >> gs;
+  const uint32_t r = (uint32_t)lane >> gs, gl = (uint32_t)lane & (G - 1u);
   const uint32_t slot = it.id + r;
-  int32_t h[L];
+  int32_t h[L], sw = 0;
 #pragma unroll
   for (int j = 0; j < L; ++j) h[j] = 0;
 #pragma unroll
@@ -262,36 +272,44 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it, int
     if (gl + (uint32_t)k * G < it.len4) {
       const uint32_t wv = ENC == kEncWide ? f.w[k < Fetched<L, ENC>::KW ? k : 0] : 0u;
       if (USE_LDS)
-        accumulate4<L, ENC>(h, f.e[k], wv, lds, woff);
+        accumulate4<L, ENC>(h, sw, f.e[k], wv, lds, woff);
       else
-        accumulate4<L, ENC>(h, f.e[k], wv, a.spins, 0u);
+        accumulate4<L, ENC>(h, sw, f.e[k], wv, a.spins, 0u);
     }
   }
   // rows longer than the prefetch depth: the rest of the chunks, four loads in flight
+  const uint4 *blk = a.entries + it.base4;
+  const uint32_t *wblk = ENC == kEncWide ? a.wts4 + it.base4 : nullptr;
   for (uint32_t q0 = gl + (uint32_t)KM * G; q0 < it.len4; q0 += 4u * G) {
     uint4 x[4];
     uint32_t wv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const uint32_t q = q0 + (uint32_t)k * G;
-      const size_t idx = (size_t)it.base4 + (size_t)(q < it.len4 ? q : q0) * K + r;
-      x[k] = a.entries[idx];
-      wv[k] = ENC == kEncWide ? a.wts4[idx] : 0u;
+      const uint32_t idx = ((q < it.len4 ? q : q0) << ks) + r;
+      x[k] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + idx * 16u);
+      wv[k] = ENC == kEncWide ? *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(wblk) + idx * 4u)
+                              : 0u;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (q0 + (uint32_t)k * G < it.len4) {
         if (USE_LDS)
-          accumulate4<L, ENC>(h, x[k], wv[k], lds, woff);
+          accumulate4<L, ENC>(h, sw, x[k], wv[k], lds, woff);
         else
-          accumulate4<L, ENC>(h, x[k], wv[k], a.spins, 0u);
+          accumulate4<L, ENC>(h, sw, x[k], wv[k], a.spins, 0u);
       }
     }
   }
   for (uint32_t off = 1; off < G; off <<= 1) {
 #pragma unroll
     for (int j = 0; j < L; ++j) h[j] += __shfl_xor(h[j], (int)off);
+    if (ENC != kEncPm1) sw += __shfl_xor(sw, (int)off);
   }
+  // counts to fields
+  const int32_t base = ENC == kEncPm1 ? (int32_t)(it.len4 * 4u) : sw;
+#pragma unroll
+  for (int j = 0; j < L; ++j) h[j] = 2 * h[j] - base;
   const uint32_t bit0 = slot * L;
   const uint32_t sh = bit0 & 31;
   const uint32_t own = (f.ownw >> sh) & lmask<L>();
@@ -376,13 +394,16 @@ __device__ __forceinline__ void restage(const AnnealArgs &a, uint32_t *lds, uint
 
 template <int L, int ENC, bool USE_LDS>
 __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
-  extern __shared__ uint32_t lds[];
+  // spin mirror, then the barrier verdict word
+  __shared__ uint32_t mirror[USE_LDS ? kLdsBudget / 4 + 4 : 4];
+  uint32_t *const lds = mirror;
   constexpr int kWaves = kAnnealBlock / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wib = threadIdx.x / kWave;
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int gw = blockIdx.x * kWaves + wib;
   const bool multi = gridDim.x > 1;
   const bool fenced = !USE_LDS;
+  uint32_t &s_ok = mirror[USE_LDS ? kLdsBudget / 4 : 0];
   const uint32_t n_grp = gridDim.x < 8u ? gridDim.x : 8u;
   // Pipeline shape that fits the registers: two items in flight (three
   // buffers), one item in flight unrolled, or one item in flight rolled.
@@ -502,7 +523,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           fetch<L, ENC>(a, ita, lane, fa, next_plane);
         }
         ++epoch;
-        if (!bar_wait(a.bar, epoch * n_grp, a.spin_limit, fenced)) return;
+        if (!bar_wait(a.bar, epoch * n_grp, a.spin_limit, fenced, s_ok)) return;
         if (USE_LDS) {
           restage(a, lds, run_w, a.cls_w64[ph + 1], threadIdx.x, blockDim.x);
           __syncthreads();
@@ -532,7 +553,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           // sweeps stay synchronised
           bar_arrive(a.bar, fenced);
           ++epoch;
-          if (!bar_wait(a.bar, epoch * n_grp, a.spin_limit, fenced)) return;
+          if (!bar_wait(a.bar, epoch * n_grp, a.spin_limit, fenced, s_ok)) return;
         }
       } else {
         // one workgroup: its LDS copy is current
@@ -561,7 +582,7 @@ template <int L, int ENC, int W>
 __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   extern __shared__ uint32_t lds[];
   const int lane = threadIdx.x & (kWave - 1);
-  const int wib = threadIdx.x / kWave;
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const uint32_t bin = blockIdx.x % (uint32_t)args.n_bins;
   const uint32_t grp = blockIdx.x / (uint32_t)args.n_bins;
   AnnealArgs a = args;
@@ -712,9 +733,9 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs a) {
         int32_t w;
         uint32_t nb;
         if (ENC == kEncPm1) {
-          if (x == kSentinel) continue;
-          w = (x & kSignBit) ? -1 : 1;
           nb = x & ~kSignBit;
+          if (nb == slot) continue;  // padding
+          w = (x & kSignBit) ? -1 : 1;
         } else if (ENC == kEncW8) {
           w = (int32_t)(int8_t)(x >> 24);
           nb = x & 0xFFFFFFu;
@@ -733,7 +754,7 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs a) {
   e_sum = wave_sum(e_sum);
   c_sum = wave_sum(c_sum);
   __shared__ long long s_e[4], s_c[4];
-  const int wib = threadIdx.x / kWave;
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   if (lane == 0) { s_e[wib] = e_sum; s_c[wib] = c_sum; }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -753,14 +774,11 @@ hipError_t set_lds_limit(K kernel, size_t bytes) {
 template <int L, int ENC, bool USE_LDS>
 hipError_t launch_anneal_t(const AnnealArgs &a, int grid, size_t lds_bytes, hipStream_t s) {
   auto kern = k_anneal<L, ENC, USE_LDS>;
-  if (USE_LDS) {
-    hipError_t e = set_lds_limit(kern, lds_bytes);
-    if (e != hipSuccess) return e;
-  }
+  if (lds_bytes > kLdsBudget) return hipErrorInvalidValue;
   AnnealArgs copy = a;
   void *args[] = {&copy};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid), dim3(kAnnealBlock),
-                                    args, USE_LDS ? (unsigned)lds_bytes : 0u, s);
+                                    args, 0u, s);
 }
 
 template <int L, int ENC, int W>
@@ -775,12 +793,9 @@ hipError_t launch_batch_t(const AnnealArgs &a, int grid, size_t lds_bytes, hipSt
 template <int L, int ENC, bool USE_LDS>
 hipError_t occupancy_t(int *blocks, size_t lds_bytes) {
   auto kern = k_anneal<L, ENC, USE_LDS>;
-  if (USE_LDS) {
-    hipError_t e = set_lds_limit(kern, lds_bytes);
-    if (e != hipSuccess) return e;
-  }
+  if (lds_bytes > kLdsBudget) return hipErrorInvalidValue;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, reinterpret_cast<const void *>(kern),
-                                                      kAnnealBlock, USE_LDS ? lds_bytes : 0);
+                                                      kAnnealBlock, 0);
 }
 
 }  // namespace

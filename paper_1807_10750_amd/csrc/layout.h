@@ -11,10 +11,20 @@
 // chunks g, g + G, g + 2G, ... and every wavefront load covers 1 KiB of
 // contiguous memory.
 // An edge entry is a uint32 in one of three encodings:
-//   kEncPm1  (every weight +-1): slot | sign << 31, padding = kSentinel;
-//   kEncW8   (fewer than 2^24 slots): slot | weight << 24, padding = 0;
+//   kEncPm1  (every weight +-1): slot | sign << 31;
+//   kEncW8   (fewer than 2^24 slots): slot | weight << 24;
 //   kEncWide (otherwise): slot only, plus one int8 weight per entry in a
-//            separate stream, padding = slot 0 with weight 0.
+//            separate stream.
+// Padding entries name the row's own slot (graphs have no self-loops, so an
+// entry naming its own row is padding and nothing else).  With general
+// weights a pad has weight 0.  With +-1 weights the kernel counts the
+// entries whose neighbour bit differs from the sign bit, c, and takes the
+// field as 2c - (entries in the row, pads included): the pads come in pairs
+// (own, +1), (own, -1), which add exactly one to c whatever the spin, and
+// an odd number of pads ends with one (own, +1), which adds the row's own
+// bit.  For an odd degree that single pad moves the (odd, hence nonzero)
+// field by +1 towards the current spin, so the sign of the field, and the
+// tie rule, come out as without padding.
 //
 // Flip draws: one Philox block per (vertex, replica, 4 sweeps).  The sweep
 // that computes a block uses its word for itself and stores the flip bits of
@@ -30,7 +40,6 @@
 
 namespace ising {
 
-constexpr uint32_t kSentinel = 0xFFFFFFFFu;
 constexpr uint32_t kSignBit = 0x80000000u;
 
 // Chunks of 4 entries each lane prefetches per item; bounds the degree of a

@@ -248,9 +248,8 @@ int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_
       }
       L.phase_items[c + 1] = (uint32_t)L.items.size();
     }
-    // fill the entry stream
-    const uint32_t pad = L.enc == kEncPm1 ? kSentinel : 0u;
-    L.entries.assign(chunks * 4, pad);
+    // fill the entry stream; padding names the row's own slot (see layout.h)
+    L.entries.assign(chunks * 4, 0u);
     if (L.enc == kEncWide) L.wts.assign(chunks * 4, 0);
     for (const Item &it : L.items) {
       const uint32_t K = 64 / it.g;
@@ -258,10 +257,15 @@ int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_
         const int64_t slot = (int64_t)it.id + r;
         if (slot >= L.n_slots) break;
         const int32_t v = L.vid[slot];
-        if (v < 0) continue;
-        int64_t q = 0;
-        for (int64_t k = rp[v]; k < rp[v + 1]; ++k, ++q) {
+        const int64_t deg = v < 0 ? 0 : rp[v + 1] - rp[v];
+        for (int64_t q = 0; q < (int64_t)it.len4 * 4; ++q) {
           const uint64_t pos = ((uint64_t)it.base4 + (uint64_t)(q / 4) * K + r) * 4 + (q % 4);
+          if (q >= deg) {
+            const bool odd = ((q - deg) & 1) != 0;
+            L.entries[pos] = (uint32_t)slot | (L.enc == kEncPm1 && odd ? kSignBit : 0u);
+            continue;
+          }
+          const int64_t k = rp[v] + q;
           const uint32_t nb = (uint32_t)L.slot_of[g.col[k]];
           if (L.enc == kEncPm1) {
             L.entries[pos] = nb | (g.w[k] < 0 ? kSignBit : 0u);
@@ -371,13 +375,35 @@ bool check_layout(const HostLayout &L, std::string *msg) {
       return false;
     }
   }
-  for (size_t k = 0; k < L.entries.size(); ++k) {
-    const uint32_t x = L.entries[k];
-    if (L.enc == kEncPm1 && x == kSentinel) continue;
-    const uint32_t slot = L.enc == kEncPm1 ? (x & ~kSignBit) : (L.enc == kEncW8 ? (x & 0xFFFFFFu) : x);
-    if ((int64_t)slot >= L.n_slots || L.vid[slot] < 0) {
-      *msg = "layout entry " + std::to_string(k) + " names a bad slot";
-      return false;
+  // every entry names a real vertex or is padding on its own row; +-1
+  // padding is pairs of opposite signs plus at most one unsigned entry
+  for (size_t i = 0; i < L.items.size(); ++i) {
+    const Item &it = L.items[i];
+    const uint32_t K = 64 / it.g;
+    for (uint32_t r = 0; r < K; ++r) {
+      const uint32_t own = it.id + r;
+      int64_t pad_plus = 0, pad_minus = 0;
+      for (uint64_t q = 0; q < (uint64_t)it.len4 * 4; ++q) {
+        const uint64_t pos = ((uint64_t)it.base4 + (q / 4) * K + r) * 4 + (q % 4);
+        const uint32_t x = L.entries[pos];
+        const uint32_t slot = L.enc == kEncPm1 ? (x & ~kSignBit) : (L.enc == kEncW8 ? (x & 0xFFFFFFu) : x);
+        bool ok;
+        if (slot == own) {
+          const bool neg = L.enc == kEncPm1 && (x & kSignBit) != 0;
+          (neg ? pad_minus : pad_plus) += 1;
+          ok = L.enc == kEncPm1 || (L.enc == kEncW8 ? (x >> 24) == 0 : L.wts[pos] == 0);
+        } else {
+          ok = (int64_t)slot < L.n_slots && L.vid[slot] >= 0;
+        }
+        if (!ok) {
+          *msg = "layout entry " + std::to_string(pos) + " names a bad slot";
+          return false;
+        }
+      }
+      if (L.enc == kEncPm1 && pad_plus != pad_minus && pad_plus != pad_minus + 1) {
+        *msg = "layout padding of item " + std::to_string(i) + " is unbalanced";
+        return false;
+      }
     }
   }
   for (int64_t p = 0; p < (int64_t)L.n_bins * L.n_phases; ++p)

@@ -27,10 +27,12 @@
  *     cut     cut = sum over undirected edges with s_u != s_v of w_uv,
  *     so that 2 cut = W - E with W = sum of w over undirected edges.
  *   - Random flips: spin v of replica r in sweep t flips after its update
- *     iff x < T[t], x = word 0 of Philox4x32-10 with counter {v, t, r, 0}
- *     and key {low32(seed), high32(seed)}; T[t] is the flip probability
- *     F_p scaled to 2^32 (ISING_SCHED_*).  Random initial spins use counter
- *     {v, 0, r, 1}: s = +1 iff bit 31 of word 0 is set.
+ *     iff x < T[t], x = word (t mod 4) of the Philox4x32-10 block with
+ *     counter {v, floor(t / 4), r, 0} and key {low32(seed), high32(seed)}
+ *     (one block serves four consecutive sweeps); T[t] is the flip
+ *     probability F_p scaled to 2^32 (ISING_SCHED_*).  Random initial
+ *     spins of replica r use word (r mod 4) of the block with counter
+ *     {v, 0, floor(r / 4), 1}: s = +1 iff its bit 31 is set.
  *   - Replicas: a handle anneals R independent copies of the spins of one
  *     graph; spin arrays are int8 [R][n], replica-major, values +1 / -1.
  *   - Pointers: every graph or spin pointer may be host or device memory;

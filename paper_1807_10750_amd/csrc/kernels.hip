@@ -68,6 +68,28 @@ __device__ __forceinline__ void st_coherent64(unsigned long long *p, unsigned lo
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Tables that no kernel writes while it runs (items, wave ranges, class
+// word ranges, thresholds) are read through the constant address space, so
+// wave-uniform reads become scalar loads.
+typedef const __attribute__((address_space(4))) uint32_t ro_u32;
+__device__ __forceinline__ uint32_t ro(const uint32_t *p, size_t i) { return ((ro_u32 *)p)[i]; }
+__device__ __forceinline__ uint32_t ro(const int32_t *p, size_t i) {
+  return ((ro_u32 *)reinterpret_cast<const uint32_t *>(p))[i];
+}
+// Wave-uniform copy of a value the compiler may hold per lane (a value merged
+// after a divergent branch), so that what depends on it stays scalar.
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ Item uni(const Item &it) { return Item{uni(it.id), uni(it.base4), uni(it.len4), uni(it.g)}; }
+
+// Item i of a table; the address is made wave-uniform so the read is a
+// scalar load (waited for on its own counter, not behind the entry loads).
+__device__ __forceinline__ Item ro_item(const Item *p, uint32_t i) {
+  const uint64_t addr = reinterpret_cast<uint64_t>(p) + 16ull * i;
+  const uint64_t ua = ((uint64_t)uni((uint32_t)(addr >> 32)) << 32) | uni((uint32_t)addr);
+  ro_u32 *q = (ro_u32 *)reinterpret_cast<const uint32_t *>(ua);
+  return Item{q[0], q[1], q[2], q[3]};
+}
+
 template <int L>
 __device__ __forceinline__ uint32_t lmask() {
   return L == 32 ? 0xFFFFFFFFu : ((1u << L) - 1u);
@@ -140,7 +162,7 @@ __device__ __forceinline__ uint32_t draw_flips(int32_t v, uint32_t t, const Anne
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const uint32_t tk = 4u * b + (uint32_t)k;
-    Tk[k] = ((uint32_t)k >= w && (int64_t)tk < a.t_end) ? a.thr[tk] : 0u;
+    Tk[k] = ((uint32_t)k >= w && (int64_t)tk < a.t_end) ? ro(a.thr, tk) : 0u;
   }
   uint32_t now = 0;
   later[0] = later[1] = later[2] = 0u;
@@ -209,7 +231,7 @@ __device__ __forceinline__ bool bar_wait(uint32_t *bar, uint32_t target, uint32_
     s_ok = ok;
   }
   __syncthreads();
-  return s_ok != 0;
+  return __builtin_amdgcn_readfirstlane(s_ok) != 0u;  // wave-uniform, so loops stay scalar
 }
 
 // ---------------------------------------------------------------------------
@@ -230,7 +252,8 @@ struct Fetched {
 // share of the sliced-ELL chunks (chunks g, g + G, ...).
 // plane: flip plane to read for this item's sweep (-1 when the sweep draws).
 template <int L, int ENC>
-__device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it, int lane, Fetched<L, ENC> &f, int plane) {
+__device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, int lane, Fetched<L, ENC> &f, int plane) {
+  const Item it = uni(it_in);
   constexpr int KM = Fetched<L, ENC>::KM;
   const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs, K = 64u >> gs;
   const uint32_t r = (uint32_t)lane >> gs, gl = (uint32_t)lane & (G - 1u);
@@ -258,8 +281,9 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it, int l
 // first sweep of the call); otherwise the flip bits come from the planes.
 // woff: the spin word that lds[0] holds (0 when LDS mirrors the whole state).
 template <int L, int ENC, bool USE_LDS>
-__device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it, int lane, const Fetched<L, ENC> &f,
+__device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, int lane, const Fetched<L, ENC> &f,
                                         uint32_t *lds, uint32_t t, bool draws, uint32_t woff = 0) {
+  const Item it = uni(it_in);
   constexpr int KM = Fetched<L, ENC>::KM;
   const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs, K = 64u >> gs;
   const uint32_t r = (uint32_t)lane >> gs, gl = (uint32_t)lane & (G - 1u);
@@ -420,11 +444,11 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   uint32_t epoch = 0;
   uint32_t run_w = 0;  // first spin word written since the last grid barrier
   const size_t stride = (size_t)a.nw + 1;
-  uint32_t ib = a.wave_ptr[gw], ie = a.wave_ptr[gw + 1];
+  uint32_t ib = ro(a.wave_ptr, gw), ie = ro(a.wave_ptr, gw + 1);
   Fetched<L, ENC> fa, fb, fc;
   Item ita;
   if (ib < ie) {
-    ita = a.items[ib];
+    ita = ro_item(a.items, ib);
     fetch<L, ENC>(a, ita, lane, fa, plane_of(a.t_begin));
   }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
@@ -433,45 +457,54 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
       // Items of this phase.  On entry fa holds the loads of item ib.  The
       // loop is unrolled by the pipeline depth so the buffers change roles
       // without register copies (a copy would wait for its loads).
+      // pre: the metadata of the next item to fetch, read one step before
+      // its fetch so the scalar load is not waited for at the fetch
       if (kDeep) {
         // two items ahead: fa, fb, fc in rotation
-        Item itb, itc;
+        Item itb, itc, pre;
         if (ib + 1 < ie) {
-          itb = a.items[ib + 1];
+          itb = ro_item(a.items, ib + 1);
           fetch<L, ENC>(a, itb, lane, fb, plane);
         }
+        if (ib + 2 < ie) pre = ro_item(a.items, ib + 2);
         for (uint32_t i = ib; i < ie; i += 3) {
           if (i + 2 < ie) {
-            itc = a.items[i + 2];
+            itc = pre;
             fetch<L, ENC>(a, itc, lane, fc, plane);
+            if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
           compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
           if (i + 1 >= ie) break;
           if (i + 3 < ie) {
-            ita = a.items[i + 3];
+            ita = pre;
             fetch<L, ENC>(a, ita, lane, fa, plane);
+            if (i + 4 < ie) pre = ro_item(a.items, i + 4);
           }
           compute<L, ENC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0);
           if (i + 2 >= ie) break;
           if (i + 4 < ie) {
-            itb = a.items[i + 4];
+            itb = pre;
             fetch<L, ENC>(a, itb, lane, fb, plane);
+            if (i + 5 < ie) pre = ro_item(a.items, i + 5);
           }
           compute<L, ENC, USE_LDS>(a, itc, lane, fc, lds, (uint32_t)t, plane < 0);
         }
       } else if (kUnrolled) {
         // one item ahead: fa, fb in rotation
-        Item itb;
+        Item itb, pre;
+        if (ib + 1 < ie) pre = ro_item(a.items, ib + 1);
         for (uint32_t i = ib; i < ie; i += 2) {
           if (i + 1 < ie) {
-            itb = a.items[i + 1];
+            itb = pre;
             fetch<L, ENC>(a, itb, lane, fb, plane);
+            if (i + 2 < ie) pre = ro_item(a.items, i + 2);
           }
           compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
           if (i + 1 >= ie) break;
           if (i + 2 < ie) {
-            ita = a.items[i + 2];
+            ita = pre;
             fetch<L, ENC>(a, ita, lane, fa, plane);
+            if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
           compute<L, ENC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0);
         }
@@ -481,7 +514,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           const bool more = i + 1 < ie;
           Item itb;
           if (more) {
-            itb = a.items[i + 1];
+            itb = ro_item(a.items, i + 1);
             fetch<L, ENC>(a, itb, lane, fb, plane);
           }
           compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
@@ -496,51 +529,52 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
       const int32_t nph = last_phase ? 0 : ph + 1;
       const bool done = last_phase && t + 1 == a.t_end;
       const int next_plane = last_phase ? plane_of(t + 1) : plane;
-      ib = a.wave_ptr[(size_t)nph * stride + gw];
-      ie = a.wave_ptr[(size_t)nph * stride + gw + 1];
+      ib = ro(a.wave_ptr, (size_t)nph * stride + gw);
+      ie = ro(a.wave_ptr, (size_t)nph * stride + gw + 1);
       if (done) ie = ib;
       if (multi && !a.async_mode) {
         // deterministic.  A run of small phases goes to workgroup 0 alone,
         // which separates them by workgroup syncs; every other phase, and
         // the end of such a run, is a grid barrier after which all
         // workgroups refresh the classes written since the previous one.
-        if (!a.local[ph]) run_w = a.cls_w64[ph];
-        if (a.local[ph] && a.local[nph] && !last_phase) {
+        if (!ro(a.local, ph)) run_w = ro(a.cls_w64, ph);
+        if (ro(a.local, ph) && ro(a.local, nph) && !last_phase) {
           if (blockIdx.x == 0) {
             if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
             if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           }
           if (ib < ie) {
-            ita = a.items[ib];
+            ita = ro_item(a.items, ib);
             fetch<L, ENC>(a, ita, lane, fa, next_plane);
           }
           continue;
         }
         bar_arrive(a.bar, fenced);
         if (ib < ie) {
-          ita = a.items[ib];
+          ita = ro_item(a.items, ib);
           fetch<L, ENC>(a, ita, lane, fa, next_plane);
         }
         ++epoch;
         if (!bar_wait(a.bar, epoch * n_grp, a.spin_limit, fenced, s_ok)) return;
         if (USE_LDS) {
-          restage(a, lds, run_w, a.cls_w64[ph + 1], threadIdx.x, blockDim.x);
+          restage(a, lds, run_w, ro(a.cls_w64, ph + 1), threadIdx.x, blockDim.x);
           __syncthreads();
         }
-        run_w = a.cls_w64[ph + 1];
+        run_w = ro(a.cls_w64, ph + 1);
       } else if (multi) {
         // async: no wait inside a sweep.  Each wave refreshes its share of
         // the phase's spin words from the global state, skipping the words
         // only this workgroup writes (its LDS copy of those is the freshest).
         if (ib < ie) {
-          ita = a.items[ib];
+          ita = ro_item(a.items, ib);
           fetch<L, ENC>(a, ita, lane, fa, next_plane);
         }
         if (USE_LDS) {
-          const uint32_t *own = a.own_w64 + ((size_t)ph * gridDim.x + blockIdx.x) * 2;
-          const uint32_t b = a.cls_w64[ph], e = a.cls_w64[ph + 1];
-          const uint32_t ol = own[0] > b ? own[0] : b, oh = own[1] < e ? own[1] : e;
+          const size_t oi = ((size_t)ph * gridDim.x + blockIdx.x) * 2;
+          const uint32_t o0 = ro(a.own_w64, oi), o1 = ro(a.own_w64, oi + 1);
+          const uint32_t b = ro(a.cls_w64, ph), e = ro(a.cls_w64, ph + 1);
+          const uint32_t ol = o0 > b ? o0 : b, oh = o1 < e ? o1 : e;
           const uint32_t first = (uint32_t)(wib * kWave + lane);
           if (ol < oh) {
             restage(a, lds, b, ol, first, blockDim.x);
@@ -550,15 +584,18 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           }
         }
         if (last_phase && !done) {
-          // sweeps stay synchronised
+          // sweeps stay within async_slack of each other: after its sweep
+          // k, a workgroup waits for every workgroup's sweep k - slack
           bar_arrive(a.bar, fenced);
           ++epoch;
-          if (!bar_wait(a.bar, epoch * n_grp, a.spin_limit, fenced, s_ok)) return;
+          if (epoch > a.async_slack &&
+              !bar_wait(a.bar, (epoch - a.async_slack) * n_grp, a.spin_limit, fenced, s_ok))
+            return;
         }
       } else {
         // one workgroup: its LDS copy is current
         if (ib < ie) {
-          ita = a.items[ib];
+          ita = ro_item(a.items, ib);
           fetch<L, ENC>(a, ita, lane, fa, next_plane);
         }
         if (!a.async_mode || last_phase) {
@@ -590,17 +627,17 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   a.flips = args.flips + (size_t)grp * 3 * args.n_words;
   a.r0 = grp * (uint32_t)L;
   a.r_count = args.r_total - a.r0 < (uint32_t)L ? args.r_total - a.r0 : (uint32_t)L;
-  const uint32_t w0 = args.bin_words[bin], w1 = args.bin_words[bin + 1];
+  const uint32_t w0 = ro(args.bin_words, bin), w1 = ro(args.bin_words, bin + 1);
   for (uint32_t i = threadIdx.x; i < w1 - w0; i += blockDim.x) lds[i] = ld_coherent(a.spins + w0 + i);
   __syncthreads();
   if (a.n_phases <= 0 || a.t_begin >= a.t_end) return;
   auto plane_of = [&](int64_t t) -> int { return (t == a.t_begin || (t & 3) == 0) ? -1 : (int)(t & 3) - 1; };
   const uint32_t *wp = a.wave_ptr + (size_t)bin * a.n_phases * (W + 1) + wib;
-  uint32_t ib = wp[0], ie = wp[1];
+  uint32_t ib = ro(wp, 0), ie = ro(wp, 1);
   Fetched<L, ENC> fa, fb;
   Item ita;
   if (ib < ie) {
-    ita = a.items[ib];
+    ita = ro_item(a.items, ib);
     fetch<L, ENC>(a, ita, lane, fa, plane_of(a.t_begin));
   }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
@@ -610,13 +647,13 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
       Item itb;
       for (uint32_t i = ib; i < ie; i += 2) {
         if (i + 1 < ie) {
-          itb = a.items[i + 1];
+          itb = ro_item(a.items, i + 1);
           fetch<L, ENC>(a, itb, lane, fb, plane);
         }
         compute<L, ENC, true>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, w0);
         if (i + 1 >= ie) break;
         if (i + 2 < ie) {
-          ita = a.items[i + 2];
+          ita = ro_item(a.items, i + 2);
           fetch<L, ENC>(a, ita, lane, fa, plane);
         }
         compute<L, ENC, true>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, w0);
@@ -624,11 +661,11 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
       const bool last_phase = ph + 1 == a.n_phases;
       const int32_t nph = last_phase ? 0 : ph + 1;
       const bool done = last_phase && t + 1 == a.t_end;
-      ib = wp[(size_t)nph * (W + 1)];
-      ie = wp[(size_t)nph * (W + 1) + 1];
+      ib = ro(wp, (size_t)nph * (W + 1));
+      ie = ro(wp, (size_t)nph * (W + 1) + 1);
       if (done) ie = ib;
       if (ib < ie) {
-        ita = a.items[ib];
+        ita = ro_item(a.items, ib);
         fetch<L, ENC>(a, ita, lane, fa, last_phase ? plane_of(t + 1) : plane);
       }
       if (!a.async_mode || last_phase) __syncthreads();
@@ -716,7 +753,7 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs a) {
   const uint32_t n_waves = gridDim.x * blockDim.x / kWave;
   long long e_sum = 0, c_sum = 0;
   for (uint32_t i = wave; i < a.n_items; i += n_waves) {
-    const Item it = a.items[i];
+    const Item it = ro_item(a.items, i);
     const uint32_t G = it.g, K = 64u / G;
     const uint32_t r = (uint32_t)lane / G, gl = (uint32_t)lane & (G - 1u);
     const uint32_t slot = it.id + r;

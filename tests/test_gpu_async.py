@@ -78,6 +78,9 @@ CASES = [
     ("er800_one", lambda: G.erdos_renyi(800, 0.06, "one", 1), 1000, {}),
     ("torus200_pm1", lambda: G.torus(200, 200), 1000, {}),
     ("powerlaw100k_pm1", lambda: G.powerlaw_chung_lu(100_000, seed=5), 200, {}),
+    # sweeps in lock step (no run-ahead) and a wider run-ahead window
+    ("reg3_pm1_20k_slack0", lambda: G.random_regular(20000, 3, "pm1", 3), 300, dict(ISING_ASYNC_SLACK=0)),
+    ("powerlaw100k_slack4", lambda: G.powerlaw_chung_lu(100_000, seed=6), 200, dict(ISING_ASYNC_SLACK=4)),
 ]
 
 

@@ -45,16 +45,69 @@ KERNEL_SOURCES = ["paper_1807_10750_amd/csrc/kernels.hip", "paper_1807_10750_amd
 
 
 def make_graph(name):
+    """(graph, first vertex of each member graph + [n]) for a workload."""
     from paper_1807_10750_amd import graphs as G
-    if name == "powerlaw1m":
-        return G.powerlaw_chung_lu(1_000_000, alpha=2.5, mean_deg=8.0, max_deg=2000, weights="pm1", seed=1)
-    if name == "torus200":
-        return G.torus(200, 200, weights="pm1", seed=1)
-    if name == "er800":
-        return G.erdos_renyi(800, 0.06, "one", 1)
     if name == "batch4096":
-        return G.disjoint_union(G.batched_erdos_renyi(4096, 64, 4096, 3.0, 20.0, "pm1", 1))
-    raise ValueError(name)
+        parts = G.batched_erdos_renyi(4096, 64, 4096, 3.0, 20.0, "pm1", 1)
+        offsets = np.concatenate([[0], np.cumsum([p.n for p in parts])]).astype(np.int64)
+        return G.disjoint_union(parts), offsets
+    if name == "powerlaw1m":
+        g = G.powerlaw_chung_lu(1_000_000, alpha=2.5, mean_deg=8.0, max_deg=2000, weights="pm1", seed=1)
+    elif name == "torus200":
+        g = G.torus(200, 200, weights="pm1", seed=1)
+    elif name == "er800":
+        g = G.erdos_renyi(800, 0.06, "one", 1)
+    else:
+        raise ValueError(name)
+    return g, np.array([0, g.n], np.int64)
+
+
+def member_cuts(g, offsets, spins):
+    """Cut of every member graph in every replica: int64 [R, members]."""
+    u, v, w = g.edges()
+    member = np.searchsorted(offsets, u, side="right") - 1
+    out = np.zeros((spins.shape[0], len(offsets) - 1), np.int64)
+    for r in range(spins.shape[0]):
+        cut_e = spins[r, u] != spins[r, v]
+        out[r] = np.bincount(member[cut_e], weights=w[cut_e].astype(np.int64), minlength=len(offsets) - 1)
+    return out
+
+
+def time_to_cut(I, torch, gr, g, offsets, M, R, mode, ladder, seed=7):
+    """GPU time until each member graph's median plain cut is reached.
+
+    The plain run anneals every member with the full schedule of M sweeps;
+    member i's target is the median of its R replicas' final cuts.  Each
+    shorter linear schedule M' of the ladder is then run from the same
+    random start, and member i counts as reached when its best replica cut
+    is at least its target.  Returned: per M', the anneal's GPU time and the
+    fraction of members reached, and the GPU time of the shortest M' at which
+    half and all members are reached (None if none is).
+    """
+    stream = torch.cuda.current_stream()
+    rows = []
+    target = None
+    for Mp in sorted(set(ladder + [M]), reverse=True):
+        sch = I.make_schedule(0.1, 0.0, Mp)
+        gr.randomize(seed)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        gr.anneal(sch, seed, mode)
+        b.record(stream)
+        torch.cuda.synchronize()
+        cuts = member_cuts(g, offsets, gr.spins())
+        if target is None:
+            target = np.median(cuts, axis=0)
+        reached = float(np.mean(cuts.max(axis=0) >= target))
+        rows.append({"sweeps": Mp, "gpu_ms": a.elapsed_time(b), "reached": reached})
+        print(f"# time-to-cut: {Mp} sweeps {rows[-1]['gpu_ms']:.2f} ms, reached {reached:.3f}",
+              file=sys.stderr, flush=True)
+    rows.sort(key=lambda r: r["sweeps"])
+    first = lambda frac: next((r["gpu_ms"] for r in rows if r["reached"] >= frac), None)
+    return {"definition": "GPU ms of the shortest linear schedule (p 0.1 -> 0) whose best-of-R cut reaches "
+                          "the median plain cut of the full schedule, per member graph",
+            "members": int(len(offsets) - 1), "replicas": R, "plain_sweeps": M,
+            "median_member_ms": first(0.5), "all_members_ms": first(1.0), "ladder": rows}
 
 
 def sources_digest():
@@ -142,6 +195,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=None, help="override the schedule length")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--p-start", type=float, default=0.1, help="initial flip probability of the linear schedule")
+    ap.add_argument("--time-to-cut", action="store_true",
+                    help="also measure time-to-cut over a ladder of shorter schedules (untimed for 'value')")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_anneal_traffic_powerlaw1m_async.txt"),
                     help="rocprofv3 counter summary giving HBM bytes per anneal launch")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -170,7 +225,7 @@ def main():
     torch.cuda.set_device(0)
 
     t0 = time.perf_counter()
-    g = make_graph(args.workload)
+    g, offsets = make_graph(args.workload)
     gen_s = time.perf_counter() - t0
     print(f"# graph {args.workload}: n={g.n} m={g.m} generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
@@ -246,13 +301,16 @@ def main():
                    "lds_spins": bool(info["uses_lds"]), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_anneal", "anneal_ms_mean": float(np.mean(anneal_ms)),
+                     "kernel": "k_anneal_batch" if info["bins"] > 0 else "k_anneal",
+                     "anneal_ms_mean": float(np.mean(anneal_ms)),
                      "anneal_ms_min": float(np.min(anneal_ms)),
                      "algorithmic_bytes_per_launch": alg, "moved_bytes_per_launch": moved},
         "final_cut_last_step": int(cuts[0]),
         "sources_sha256": sources_digest(),
         "create_s": create_s,
     }
+    if args.time_to_cut:
+        out["time_to_cut"] = time_to_cut(I, torch, gr, g, offsets, M, R, mode, [M // 16, M // 8, M // 4, M // 2])
     if args.cpu_budget > 0:
         print("# cpu baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, M, R, 1000, args.cpu_budget)

@@ -41,6 +41,16 @@
  *   - Streams: each call is ordered on the caller's stream (a hipStream_t
  *     passed as void*; NULL is the default stream).  Calls that return
  *     values into host memory synchronise that stream before returning.
+ *   - Graph capture: isingRandomizeSpins, isingAnneal with a schedule the
+ *     handle has already run (its thresholds are then cached on the
+ *     device), and isingCut / isingGetSpins into device memory enqueue only
+ *     kernels, so a HIP graph can capture them.  A new schedule uploads its
+ *     table first and synchronises the stream, which capture does not allow.
+ *     While the stream captures, the multi-workgroup anneal becomes an
+ *     ordinary kernel node; its grid never exceeds what fits on the device
+ *     at once, and if some workgroups still cannot start (other work holds
+ *     the device) its grid barrier gives up after a bounded number of polls
+ *     and the next synchronising call reports ISING_ERR_DEVICE.
  *   - Ownership: isingCreate copies its inputs; the caller may free them on
  *     return.  The handle owns every device buffer; isingDestroy frees them.
  *   - Errors: no function aborts, throws or exits.  Each returns an

@@ -813,6 +813,16 @@ hipError_t launch_anneal_t(const AnnealArgs &a, int grid, size_t lds_bytes, hipS
   if (lds_bytes > kLdsBudget) return hipErrorInvalidValue;
   AnnealArgs copy = a;
   void *args[] = {&copy};
+  // Under stream capture the launch becomes an ordinary kernel node: the
+  // grid never exceeds what the occupancy query says fits at once, and the
+  // barrier's poll limit turns a grid that is not co-resident into an error.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cap);
+  if (e != hipSuccess) return e;
+  if (cap == hipStreamCaptureStatusActive) {
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kAnnealBlock), 0u, s, copy);
+    return hipGetLastError();
+  }
   return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(grid), dim3(kAnnealBlock),
                                     args, 0u, s);
 }

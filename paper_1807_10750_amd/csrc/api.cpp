@@ -4,8 +4,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ising.h"
@@ -232,6 +235,77 @@ ising_status_t check_flags(ising_graph_s *g, hipStream_t st) {
   return ISING_OK;
 }
 
+// Launch-shape tuning of the batched anneal: waves per workgroup.  Choices
+// are cached for the process by a key of the handle's shape, so handles of
+// the same shape are timed once.
+typedef std::tuple<int32_t, int64_t, int64_t, int32_t, int32_t, int32_t, size_t> TuneKey;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune_cache;
+
+// Times a short deterministic anneal of the handle with each candidate wave
+// table and returns the index of the fastest.  The spins and flip planes
+// are clobbered; the caller resets them.
+ising_status_t time_batch_shapes(ising_graph_s *g, const std::vector<std::vector<uint32_t>> &tables,
+                                 const int *waves, hipStream_t st, int *best) {
+  constexpr int kSweeps = 8;
+  uint32_t *d_tab = nullptr, *d_thr = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  size_t cap = 0;
+  for (const auto &t : tables) cap = std::max(cap, t.size());
+  ising_status_t r = dev_alloc(&d_tab, sizeof(uint32_t) * cap, "tuning table");
+  if (r == ISING_OK) r = dev_alloc(&d_thr, sizeof(uint32_t) * kSweeps, "tuning thresholds");
+  std::vector<uint32_t> thr(kSweeps);
+  for (int t = 0; t < kSweeps; ++t) thr[t] = (uint32_t)(0x0A000000u - 0x01000000u * (uint32_t)t);
+  if (r == ISING_OK) r = upload(d_thr, thr.data(), sizeof(uint32_t) * kSweeps, "tuning threshold upload");
+  if (r == ISING_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    r = fail(ISING_ERR_DEVICE, "hipEventCreate");
+  float best_ms = 0.f;
+  *best = 0;
+  for (size_t c = 0; r == ISING_OK && c < tables.size(); ++c) {
+    hipError_t e = hipMemcpyAsync(d_tab, tables[c].data(), sizeof(uint32_t) * tables[c].size(),
+                                  hipMemcpyHostToDevice, st);
+    AnnealArgs a{};
+    a.entries = reinterpret_cast<const uint4 *>(g->d_entries);
+    a.wts4 = g->d_wts4;
+    a.vid = g->d_vid;
+    a.items = g->d_items;
+    a.thr = d_thr;
+    a.bar = g->d_bar;
+    a.n_words = g->n_words;
+    a.seed_lo = 1u;
+    a.spin_limit = 1000000;
+    a.spins = g->d_spins;
+    a.flips = g->d_flips;
+    a.wave_ptr = d_tab;
+    a.bin_words = g->d_bin_words;
+    a.n_bins = g->lay.n_bins;
+    a.n_phases = g->n_colors;
+    a.r_total = (uint32_t)g->R;
+    a.t_begin = 0;
+    a.t_end = kSweeps;
+    float ms = 0.f;
+    // the first launch warms caches and code; the second is timed
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+      if (rep == 1) e = hipEventRecord(e0, st);
+      if (e == hipSuccess)
+        e = launch_anneal_batch(g->L, g->lay.enc, waves[c], a, g->lay.n_bins * g->n_groups, g->batch_lds, st);
+      if (rep == 1 && e == hipSuccess) e = hipEventRecord(e1, st);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) r = hip_fail(e, "launch-shape tuning");
+    if (r == ISING_OK && (c == 0 || ms < best_ms)) {
+      best_ms = ms;
+      *best = (int)c;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (d_tab) (void)hipFree(d_tab);
+  if (d_thr) (void)hipFree(d_thr);
+  return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -386,19 +460,29 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   }
 
   // batched mode tables
-  std::vector<uint32_t> bin_wave_ptr, bin_words;
+  // one wave table per candidate launch shape (waves per workgroup); the
+  // tuner below keeps one of them
+  static const int kWaveChoices[3] = {4, 8, 16};
+  std::vector<std::vector<uint32_t>> bin_wave_ptrs;
+  std::vector<uint32_t> bin_words;
+  int tune_forced = 0;
   if (g->batch) {
-    g->batch_waves = (int)env_int("ISING_BATCH_WAVES", 4);
-    if (g->batch_waves != 4 && g->batch_waves != 8 && g->batch_waves != 16) g->batch_waves = 4;
+    tune_forced = (int)env_int("ISING_BATCH_WAVES", 0);
+    if (tune_forced != 0 && tune_forced != 4 && tune_forced != 8 && tune_forced != 16) tune_forced = 4;
+    if (tune_forced == 0 && env_int("ISING_AUTOTUNE", 1) == 0) tune_forced = 4;
     const int32_t nc = g->n_colors;
     std::vector<uint32_t> none((size_t)nc, 0u);
     bin_words.resize((size_t)n_bins + 1);
     size_t max_words = 0;
+    bin_wave_ptrs.resize(3);
     for (int32_t b = 0; b < n_bins; ++b) {
       std::vector<int32_t> pc((size_t)nc + 1);
       for (int32_t c = 0; c <= nc; ++c) pc[c] = b * nc + c;
-      const std::vector<uint32_t> wp = partition_waves(lay, pc, g->batch_waves, none, g->batch_waves);
-      bin_wave_ptr.insert(bin_wave_ptr.end(), wp.begin(), wp.end());
+      for (int k = 0; k < 3; ++k) {
+        if (tune_forced != 0 && kWaveChoices[k] != tune_forced) continue;
+        const std::vector<uint32_t> wp = partition_waves(lay, pc, kWaveChoices[k], none, kWaveChoices[k]);
+        bin_wave_ptrs[k].insert(bin_wave_ptrs[k].end(), wp.begin(), wp.end());
+      }
       bin_words[b] = (uint32_t)((uint64_t)lay.cls_begin[(size_t)b * nc] * L / 32);
       const uint64_t end = (uint64_t)lay.cls_begin[(size_t)(b + 1) * nc] * L / 32;
       max_words = std::max<size_t>(max_words, (size_t)(end - bin_words[b]));
@@ -441,11 +525,6 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   if ((r = dev_alloc(&g->d_flips, sizeof(uint32_t) * 3 * (size_t)g->n_words * g->n_groups, "flip planes")) != ISING_OK)
     return bail(r);
   if (g->batch) {
-    if ((r = dev_alloc(&g->d_bin_wave_ptr, sizeof(uint32_t) * bin_wave_ptr.size(), "bin wave table")) != ISING_OK)
-      return bail(r);
-    if ((r = upload(g->d_bin_wave_ptr, bin_wave_ptr.data(), sizeof(uint32_t) * bin_wave_ptr.size(), "bin wave upload")) !=
-        ISING_OK)
-      return bail(r);
     if ((r = dev_alloc(&g->d_bin_words, sizeof(uint32_t) * bin_words.size(), "bin word table")) != ISING_OK) return bail(r);
     if ((r = upload(g->d_bin_words, bin_words.data(), sizeof(uint32_t) * bin_words.size(), "bin word upload")) != ISING_OK)
       return bail(r);
@@ -453,6 +532,38 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   if ((r = dev_alloc(&g->d_bar, sizeof(uint32_t) * kBarWords, "flags")) != ISING_OK) return bail(r);
   if ((r = dev_alloc(&g->d_cut, sizeof(unsigned long long) * 2 * (size_t)n_replicas + 16, "cut")) != ISING_OK) return bail(r);
   if ((r = dev_alloc(&g->d_stage, (size_t)n * (size_t)n_replicas, "spin staging")) != ISING_OK) return bail(r);
+  if (g->batch) {
+    // launch shape: forced, cached for this shape, or timed now
+    int pick = 0;
+    for (int k = 0; k < 3; ++k)
+      if (kWaveChoices[k] == tune_forced) pick = k;
+    if (tune_forced == 0) {
+      const TuneKey key{g->lay.n_bins, (int64_t)lay.items.size(), (int64_t)lay.n_slots, g->L, g->n_groups,
+                        lay.enc, g->batch_lds};
+      bool cached = false;
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+          pick = it->second;
+          cached = true;
+        }
+      }
+      if (!cached) {
+        hipError_t e = launch_fill_u32(g->d_spins, g->n_words * (uint32_t)g->n_groups, 0xFFFFFFFFu, st);
+        if (e != hipSuccess) return bail(hip_fail(e, "initialising spins"));
+        if ((r = time_batch_shapes(g, bin_wave_ptrs, kWaveChoices, st, &pick)) != ISING_OK) return bail(r);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = pick;
+      }
+    }
+    g->batch_waves = kWaveChoices[pick];
+    const std::vector<uint32_t> &tab = bin_wave_ptrs[pick];
+    if ((r = dev_alloc(&g->d_bin_wave_ptr, sizeof(uint32_t) * tab.size(), "bin wave table")) != ISING_OK)
+      return bail(r);
+    if ((r = upload(g->d_bin_wave_ptr, tab.data(), sizeof(uint32_t) * tab.size(), "bin wave upload")) != ISING_OK)
+      return bail(r);
+  }
   {
     hipError_t e = launch_fill_u32(g->d_spins, g->n_words * (uint32_t)g->n_groups, 0xFFFFFFFFu, st);
     if (e == hipSuccess) e = launch_fill_u32(g->d_bar, kBarWords, 0u, st);

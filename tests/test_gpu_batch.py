@@ -79,6 +79,22 @@ def test_batched_launch_shapes_bit_exact(I, knobs):
     assert np.array_equal(sg, so)
 
 
+def test_autotuned_launch_shape(I):
+    # the tuner picks waves per workgroup by timing; results do not depend on
+    # the pick, a forced shape skips tuning, and the switch turns it off
+    g = small_batch(60, 8)
+    picks = []
+    for knobs in (dict(), dict(), dict(ISING_BATCH_WAVES=16), dict(ISING_AUTOTUNE=0)):
+        with env(**knobs):
+            sg, Cg, Eg, so, info = run_both(I, g, 9, 50, 8)
+        assert info["bins"] >= 2
+        assert info["block"] in (256, 512, 1024)
+        assert np.array_equal(sg, so)
+        picks.append(info["block"])
+    assert picks[0] == picks[1]  # same shape: the cached choice
+    assert picks[2] == 1024 and picks[3] == 256
+
+
 def test_mixed_weights_and_isolated_components(I):
     parts = [G.erdos_renyi(200, 0.05, "int8", 1), G.empty(300), G.torus(10, 12), G.star(50, weights=-128),
              G.random_regular(400, 3, "pm1", 2), G.cycle(9)]

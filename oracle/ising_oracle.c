@@ -39,6 +39,13 @@
  *   R9  Each unordered edge counted once in W, E and the cut.
  *   R10 Self-loops and duplicate edges are rejected; int8 weights; the
  *       field fits in int32 (checked).
+ *   R14 External field (Eq. 1 and Eq. 3, which the max-cut mapping sets to
+ *       zero in Sec. III): with J = -w the quantity whose sign sets the spin
+ *       is S_v = h_v - sum_u w_vu s_u; s_v = +1 if S_v > 0, -1 if S_v < 0,
+ *       unchanged if S_v = 0 (R2); the energy is
+ *       H = sum_{u<v} w_uv s_u s_v - sum_v h_v s_v.  The cut ignores h.
+ *       h is int32 and every row must keep sum |w| + |h_v| <= 2^30 - 1, which
+ *       leaves headroom for exact integer arithmetic on 2 h.
  *   R12 The deterministic ("coloured") schedule: vertices are visited in
  *       (colour, id) order of a greedy colouring, sequentially.  Because no
  *       two vertices of one colour are adjacent, any order inside a colour
@@ -299,6 +306,19 @@ static int8_t local_update(int32_t h, int8_t s) {
   return s;
 }
 
+/* With an external field (R14): Eq. (1)-(2) give H_v(s) = -S_v s with
+ * S_v = sum_u J_vu s_u + h_v = -(sum_u w_vu s_u) + h_v; the spin takes the
+ * sign of S_v and keeps its value when S_v = 0.  field == NULL is h = 0. */
+static int8_t field_update(int64_t v, const int64_t *row_ptr, const int32_t *col, const int8_t *w,
+                           const int32_t *field, const int8_t *s_read, int8_t s_v) {
+  if (field == NULL) return local_update(local_field(v, row_ptr, col, w, s_read), s_v);
+  int64_t S = (int64_t)field[v];
+  for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) S -= (int64_t)w[k] * (int64_t)s_read[col[k]];
+  if (S > 0) return 1;
+  if (S < 0) return -1;
+  return s_v;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Deterministic anneal: Algorithm 2 with the parallel "for all" replaced   */
 /* by a sequential visit in the given order (the (colour, id) order makes   */
@@ -308,7 +328,7 @@ static int8_t local_update(int32_t h, int8_t s) {
 /* schedule (indexed by absolute sweep).                                    */
 /* ------------------------------------------------------------------------ */
 int oracle_anneal(int64_t n, const int64_t *row_ptr, const int32_t *col, const int8_t *w,
-                  const int32_t *order, int32_t R, int8_t *spins, const uint32_t *T,
+                  const int32_t *field, const int32_t *order, int32_t R, int8_t *spins, const uint32_t *T,
                   uint64_t seed, int64_t t_begin, int64_t t_end) {
   if (t_begin < 0 || t_end < t_begin) return OR_ERR_ARG;
   for (int32_t r = 0; r < R; ++r) {
@@ -316,8 +336,7 @@ int oracle_anneal(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
     for (int64_t t = t_begin; t < t_end; ++t) {
       for (int64_t i = 0; i < n; ++i) {
         int64_t v = order[i];
-        int32_t h = local_field(v, row_ptr, col, w, s);
-        s[v] = local_update(h, s[v]);
+        s[v] = field_update(v, row_ptr, col, w, field, s, s[v]);
         if (flip_draw((uint32_t)v, (uint32_t)t, (uint32_t)r, seed) < T[t]) s[v] = (int8_t)-s[v];
       }
     }
@@ -327,7 +346,7 @@ int oracle_anneal(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
 
 /* Jacobi bracket: all vertices of sweep t read the spins of sweep t-1. */
 int oracle_anneal_jacobi(int64_t n, const int64_t *row_ptr, const int32_t *col, const int8_t *w,
-                         int32_t R, int8_t *spins, const uint32_t *T, uint64_t seed,
+                         const int32_t *field, int32_t R, int8_t *spins, const uint32_t *T, uint64_t seed,
                          int64_t t_begin, int64_t t_end) {
   if (t_begin < 0 || t_end < t_begin) return OR_ERR_ARG;
   int8_t *prev = (int8_t *)malloc((size_t)(n > 0 ? n : 1));
@@ -337,8 +356,7 @@ int oracle_anneal_jacobi(int64_t n, const int64_t *row_ptr, const int32_t *col, 
     for (int64_t t = t_begin; t < t_end; ++t) {
       memcpy(prev, s, (size_t)n);
       for (int64_t v = 0; v < n; ++v) {
-        int32_t h = local_field(v, row_ptr, col, w, prev);
-        int8_t x = local_update(h, prev[v]);
+        int8_t x = field_update(v, row_ptr, col, w, field, prev, prev[v]);
         if (flip_draw((uint32_t)v, (uint32_t)t, (uint32_t)r, seed) < T[t]) x = (int8_t)-x;
         s[v] = x;
       }
@@ -353,12 +371,16 @@ int oracle_anneal_jacobi(int64_t n, const int64_t *row_ptr, const int32_t *col, 
 /*   cut = sum_{u<v, s_u != s_v} w_uv          (Eq. 4 evaluated directly)   */
 /*   E   = sum_{u<v} w_uv s_u s_v              (Eq. 5 with J = -w, R1)      */
 /* and the identity 2 cut = W - E, which follows from Eq. (4), is checked.  */
+/* With a field (R14) the energy adds -sum_v h_v s_v (Eq. 3); the cut and   */
+/* the identity use the edge part alone.                                    */
 /* ------------------------------------------------------------------------ */
 int oracle_cut(int64_t n, const int64_t *row_ptr, const int32_t *col, const int8_t *w,
-               int32_t R, const int8_t *spins, int64_t *cut, int64_t *energy) {
+               const int32_t *field, int32_t R, const int8_t *spins, int64_t *cut, int64_t *energy) {
   for (int32_t r = 0; r < R; ++r) {
     const int8_t *s = spins + (int64_t)r * n;
-    int64_t W = 0, E = 0, C = 0;
+    int64_t W = 0, E = 0, C = 0, F = 0;
+    if (field)
+      for (int64_t v = 0; v < n; ++v) F -= (int64_t)field[v] * s[v];
     for (int64_t u = 0; u < n; ++u)
       for (int64_t k = row_ptr[u]; k < row_ptr[u + 1]; ++k) {
         int64_t v = col[k];
@@ -369,7 +391,23 @@ int oracle_cut(int64_t n, const int64_t *row_ptr, const int32_t *col, const int8
       }
     if (2 * C != W - E) return OR_ERR_INTERNAL;
     cut[r] = C;
-    if (energy) energy[r] = E;
+    if (energy) energy[r] = E + F;
+  }
+  return OR_OK;
+}
+
+/* Field contract (R10, R14): every row keeps sum |w| + |h_v| <= 2^30 - 1,
+ * so S_v and twice it fit int32.  Returns OR_ERR_OVERFLOW and the first
+ * offending vertex in *bad otherwise. */
+int oracle_validate_field(int64_t n, const int64_t *row_ptr, const int8_t *w, const int32_t *field,
+                          int64_t *bad) {
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t a = field[v] < 0 ? -(int64_t)field[v] : (int64_t)field[v];
+    for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) a += w[k] < 0 ? -(int64_t)w[k] : (int64_t)w[k];
+    if (a > (INT32_MAX >> 1)) {
+      if (bad) *bad = v;
+      return OR_ERR_OVERFLOW;
+    }
   }
   return OR_OK;
 }

@@ -46,17 +46,18 @@ def lib():
         L.oracle_order.restype = None
         L.oracle_init_spins.argtypes = [i64, i32, u64, P]
         L.oracle_init_spins.restype = None
-        L.oracle_anneal.argtypes = [i64, P, P, P, P, i32, P, P, u64, i64, i64]
-        L.oracle_anneal_jacobi.argtypes = [i64, P, P, P, i32, P, P, u64, i64, i64]
-        L.oracle_cut.argtypes = [i64, P, P, P, i32, P, P, P]
+        L.oracle_anneal.argtypes = [i64, P, P, P, P, P, i32, P, P, u64, i64, i64]
+        L.oracle_anneal_jacobi.argtypes = [i64, P, P, P, P, i32, P, P, u64, i64, i64]
+        L.oracle_cut.argtypes = [i64, P, P, P, P, i32, P, P, P]
+        L.oracle_validate_field.argtypes = [i64, P, P, P, P]
         L.oracle_fields.argtypes = [i64, P, P, P, P, P]
         L.oracle_fields.restype = None
         _lib = L
     return _lib
 
 
-def _p(a: np.ndarray):
-    return a.ctypes.data_as(ctypes.c_void_p)
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
 def _csr(g):
@@ -123,9 +124,19 @@ def init_spins(n: int, R: int, seed: int) -> np.ndarray:
     return np.ascontiguousarray(s[:, :n])
 
 
-def anneal(g, order_arr, spins, T, seed: int, t_begin: int, t_end: int) -> np.ndarray:
+def _field(g, field):
+    """int32 [n] external field (None: zero field, the max-cut case)."""
+    if field is None:
+        return None
+    f = np.ascontiguousarray(field, dtype=np.int32)
+    assert f.shape == (g.n,)
+    return f if g.n else np.zeros(1, np.int32)
+
+
+def anneal(g, order_arr, spins, T, seed: int, t_begin: int, t_end: int, field=None) -> np.ndarray:
     """Deterministic sequential anneal in the given visiting order.  Returns new spins."""
     rp, c, w = _csr(g)
+    f = _field(g, field)
     s = np.array(spins, dtype=np.int8, copy=True, order="C")
     R = s.shape[0]
     o = np.ascontiguousarray(order_arr, dtype=np.int32)
@@ -136,28 +147,30 @@ def anneal(g, order_arr, spins, T, seed: int, t_begin: int, t_end: int) -> np.nd
         TT = np.zeros(1, np.uint32)
     if s.size == 0:
         return s
-    st = lib().oracle_anneal(g.n, _p(rp), _p(c), _p(w), _p(o), R, _p(s), _p(TT), seed, t_begin, t_end)
+    st = lib().oracle_anneal(g.n, _p(rp), _p(c), _p(w), _p(f), _p(o), R, _p(s), _p(TT), seed, t_begin, t_end)
     if st != OK:
         raise RuntimeError(f"oracle_anneal status {st}")
     return s
 
 
-def anneal_jacobi(g, spins, T, seed: int, t_begin: int, t_end: int) -> np.ndarray:
+def anneal_jacobi(g, spins, T, seed: int, t_begin: int, t_end: int, field=None) -> np.ndarray:
     rp, c, w = _csr(g)
+    f = _field(g, field)
     s = np.array(spins, dtype=np.int8, copy=True, order="C")
     if s.size == 0:
         return s
     TT = np.ascontiguousarray(T, dtype=np.uint32)
-    st = lib().oracle_anneal_jacobi(g.n, _p(rp), _p(c), _p(w), s.shape[0], _p(s), _p(TT), seed,
+    st = lib().oracle_anneal_jacobi(g.n, _p(rp), _p(c), _p(w), _p(f), s.shape[0], _p(s), _p(TT), seed,
                                     t_begin, t_end)
     if st != OK:
         raise RuntimeError(f"oracle_anneal_jacobi status {st}")
     return s
 
 
-def cut(g, spins):
-    """Returns (cut int64 [R], energy int64 [R])."""
+def cut(g, spins, field=None):
+    """Returns (cut int64 [R], energy int64 [R]); the energy includes -sum h s."""
     rp, c, w = _csr(g)
+    f = _field(g, field)
     s = np.ascontiguousarray(spins, dtype=np.int8)
     if s.ndim == 1:
         s = s[None, :]
@@ -166,10 +179,19 @@ def cut(g, spins):
     E = np.zeros(R, np.int64)
     if g.n == 0:
         return C, E
-    st = lib().oracle_cut(g.n, _p(rp), _p(c), _p(w), R, _p(s), _p(C), _p(E))
+    st = lib().oracle_cut(g.n, _p(rp), _p(c), _p(w), _p(f), R, _p(s), _p(C), _p(E))
     if st != OK:
         raise RuntimeError(f"oracle_cut status {st}")
     return C, E
+
+
+def validate_field(g, field):
+    """(status, first offending vertex or -1) of the field contract (R14)."""
+    rp, _, w = _csr(g)
+    f = _field(g, field)
+    bad = np.full(1, -1, np.int64)
+    st = lib().oracle_validate_field(g.n, _p(rp), _p(w), _p(f), _p(bad)) if g.n else OK
+    return int(st), int(bad[0])
 
 
 def fields(g, s) -> np.ndarray:
@@ -182,12 +204,12 @@ def fields(g, s) -> np.ndarray:
 
 
 def solve(g, seed: int, p_start: float, p_end: float, M: int, R: int = 1,
-          largest_first: bool = False, spins=None, t_begin: int = 0, t_end: int | None = None):
+          largest_first: bool = False, spins=None, t_begin: int = 0, t_end: int | None = None, field=None):
     """Whole deterministic pipeline: colour, order, thresholds, init, anneal, cut."""
     col_arr, nc = color(g, largest_first)
     o = order(col_arr, nc)
     T = thresholds(p_start, p_end, M)
     s0 = init_spins(g.n, R, seed) if spins is None else np.asarray(spins, np.int8)
-    s = anneal(g, o, s0, T, seed, t_begin, M if t_end is None else t_end)
-    C, E = cut(g, s)
+    s = anneal(g, o, s0, T, seed, t_begin, M if t_end is None else t_end, field)
+    C, E = cut(g, s, field)
     return s, C, E

@@ -26,6 +26,11 @@
  *   - energy  E   = sum over undirected edges of w_uv s_u s_v,
  *     cut     cut = sum over undirected edges with s_u != s_v of w_uv,
  *     so that 2 cut = W - E with W = sum of w over undirected edges.
+ *   - External field (optional, isingSetField): the general Ising model of
+ *     Eq. (1) and Eq. (3) adds a bias h_v on each spin.  With J = -w the
+ *     spin takes the sign of S_v = h_v - sum_u w_vu s_u (S_v = 0 keeps it)
+ *     and the energy becomes E - sum_v h_v s_v.  The cut, W and the identity
+ *     above concern the edges only.  The max-cut problem has h = 0.
  *   - Random flips: spin v of replica r in sweep t flips after its update
  *     iff x < T[t], x = word (t mod 4) of the Philox4x32-10 block with
  *     counter {v, floor(t / 4), r, 0} and key {low32(seed), high32(seed)}
@@ -148,10 +153,11 @@ ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *schedule, ui
                            ising_mode_t mode, int64_t sweep_begin, int64_t sweep_end,
                            void *stream);
 
-/* Cut value (Eq. 4) and energy (Eq. 5 with J = -w) of every replica:
- * cut int64 [R], energy int64 [R] or NULL.  Host or device outputs; host
- * outputs synchronise the stream.  Also checks 2 cut = W - E on the host
- * when the outputs are host memory. */
+/* Cut value (Eq. 4) and energy (Eq. 5 with J = -w, plus -sum h s when a
+ * field is set, Eq. 3) of every replica: cut int64 [R], energy int64 [R]
+ * or NULL.  Host or device outputs; host outputs synchronise the stream.
+ * Also checks 2 cut = W - E(edges) on the host when the outputs are host
+ * memory. */
 ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *stream);
 
 /* Copy spins out: int8 [R][n] in caller ids, host or device pointer.  A
@@ -164,6 +170,14 @@ ising_status_t isingGetColoring(ising_graph_t g, int32_t *color, int32_t *n_colo
 
 /* Sum of w over undirected edges (W in 2 cut = W - E). */
 ising_status_t isingTotalWeight(ising_graph_t g, int64_t *W);
+
+/* External field h_v of every vertex (Sec. II-A, Eq. 1 and Eq. 3): int32 [n]
+ * in caller ids, host or device pointer, copied; NULL removes the field.
+ * Every row must keep sum |w| + |h_v| <= 2^30 - 1, else
+ * ISING_ERR_OVERFLOW names the first offending vertex and the field is
+ * unchanged.  Synchronises the stream first (queued anneals finish with
+ * the old field); not for use under graph capture. */
+ising_status_t isingSetField(ising_graph_t g, const int32_t *h, void *stream);
 
 /* Layout and launch facts of a handle, for benchmarks and tests. */
 typedef struct {

@@ -115,6 +115,11 @@ struct ising_graph_s {
   uint32_t *d_bar = nullptr;   // barrier counters, error and spin-check flags (kBar*)
   unsigned long long *d_cut = nullptr;
   int8_t *d_stage = nullptr;
+  // external field: sum |w| of every row (the field contract) and -h per slot
+  std::vector<uint32_t> row_abs;
+  std::vector<uint32_t> degree;
+  int32_t *d_bias = nullptr;
+  bool has_field = false;
   // schedule cache
   bool thr_valid = false;
   double ps = -1, pe = -1;
@@ -141,7 +146,7 @@ void free_all(ising_graph_s *g) {
   void *bufs[] = {g->d_entries, g->d_wts4, g->d_vid, g->d_items, g->d_wave_ptr[0], g->d_wave_ptr[1],
                   g->d_cls_w64[0], g->d_cls_w64[1], g->d_own_w64[0], g->d_own_w64[1], g->d_flips,
                   g->d_local[0], g->d_local[1], g->d_bin_wave_ptr, g->d_bin_words,
-                  g->d_spins, g->d_thr, g->d_bar, g->d_cut, g->d_stage};
+                  g->d_spins, g->d_thr, g->d_bar, g->d_cut, g->d_stage, g->d_bias};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (g->h_thr) (void)hipHostFree(g->h_thr);
@@ -358,6 +363,18 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   int v = validate_graph(csr, &g->W, &msg);
   if (v != kPrepOk) return bail(fail((ising_status_t)v, msg));
   try {
+    g->row_abs.assign((size_t)n, 0u);
+    g->degree.assign((size_t)n, 0u);
+    for (int64_t u = 0; u < n; ++u) {
+      g->degree[(size_t)u] = (uint32_t)(csr.row_ptr[u + 1] - csr.row_ptr[u]);
+      int64_t a = 0;
+      for (int64_t k = csr.row_ptr[u]; k < csr.row_ptr[u + 1]; ++k) a += csr.w[k] < 0 ? -(int64_t)csr.w[k] : csr.w[k];
+      g->row_abs[(size_t)u] = (uint32_t)a;  // validated: at most INT32_MAX
+    }
+  } catch (const std::bad_alloc &) {
+    return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed for the row sums"));
+  }
+  try {
     g->n_colors = greedy_coloring(csr, coloring == ISING_COLOR_LARGEST_FIRST, &g->color);
   } catch (const std::bad_alloc &) {
     return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed while colouring"));
@@ -530,7 +547,8 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
       return bail(r);
   }
   if ((r = dev_alloc(&g->d_bar, sizeof(uint32_t) * kBarWords, "flags")) != ISING_OK) return bail(r);
-  if ((r = dev_alloc(&g->d_cut, sizeof(unsigned long long) * 2 * (size_t)n_replicas + 16, "cut")) != ISING_OK) return bail(r);
+  if ((r = dev_alloc(&g->d_cut, sizeof(unsigned long long) * kCutStride * (size_t)n_replicas, "cut")) != ISING_OK)
+    return bail(r);
   if ((r = dev_alloc(&g->d_stage, (size_t)n * (size_t)n_replicas, "spin staging")) != ISING_OK) return bail(r);
   if (g->batch) {
     // launch shape: forced, cached for this shape, or timed now
@@ -610,6 +628,40 @@ ising_status_t isingTotalWeight(ising_graph_t g, int64_t *W) {
   g_last_error.clear();
   if (g == nullptr || W == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
   *W = g->W;
+  return ISING_OK;
+}
+
+constexpr int64_t kFieldMax = (1LL << 30) - 1;  // bound on sum |w| + |h| per row
+
+ising_status_t isingSetField(ising_graph_t g, const int32_t *h, void *stream) {
+  g_last_error.clear();
+  if (g == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL handle");
+  DeviceGuard guard(g->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // anneals already queued on the stream may still read the old field
+  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (h == nullptr) {
+    g->has_field = false;
+    return ISING_OK;
+  }
+  std::vector<int32_t> hv;
+  ising_status_t r = fetch(&hv, h, g->n, "field");
+  if (r != ISING_OK) return r;
+  for (int64_t v = 0; v < g->n; ++v) {
+    const int64_t a = (int64_t)g->row_abs[(size_t)v] + (hv[(size_t)v] < 0 ? -(int64_t)hv[(size_t)v] : hv[(size_t)v]);
+    if (a > kFieldMax)
+      return fail(ISING_ERR_OVERFLOW, "vertex " + std::to_string(v) + ": sum |w| + |h| exceeds 2^30 - 1");
+  }
+  // per slot: 2 (-h) plus, with +-1 weights, the parity of the degree (the
+  // kernel takes the unpaired pad of an odd row back out of its field)
+  std::vector<int32_t> bias((size_t)g->lay.n_slots, 0);
+  for (int64_t v = 0; v < g->n; ++v)
+    bias[(size_t)g->lay.slot_of[(size_t)v]] =
+        -2 * hv[(size_t)v] + (g->lay.enc == kEncPm1 ? (int32_t)(g->degree[(size_t)v] & 1u) : 0);
+  if (g->d_bias == nullptr && (r = dev_alloc(&g->d_bias, sizeof(int32_t) * bias.size(), "field")) != ISING_OK)
+    return r;
+  if ((r = upload(g->d_bias, bias.data(), sizeof(int32_t) * bias.size(), "field upload")) != ISING_OK) return r;
+  g->has_field = true;
   return ISING_OK;
 }
 
@@ -712,6 +764,7 @@ ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *s, uint64_t 
   a.entries = reinterpret_cast<const uint4 *>(g->d_entries);
   a.wts4 = g->d_wts4;
   a.vid = g->d_vid;
+  a.bias = g->has_field ? g->d_bias : nullptr;
   a.items = g->d_items;
   const int m = mode == ISING_MODE_ASYNC ? 1 : 0;
   a.wave_ptr = g->d_wave_ptr[m];
@@ -771,7 +824,8 @@ ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *st
   const bool dev_e = energy != nullptr && is_device_ptr(energy);
   if (energy != nullptr && dev_cut != dev_e)
     return fail(ISING_ERR_INVALID_ARGUMENT, "cut and energy must both be host or both be device memory");
-  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(g->d_cut), 4 * (uint32_t)g->R, 0u, st), "cut reset");
+  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(g->d_cut), 2 * kCutStride * (uint32_t)g->R, 0u, st),
+          "cut reset");
   for (int grp = 0; grp < g->n_groups; ++grp)
     for (uint32_t j = 0; j < group_r_count(g, grp); ++j) {
       CutArgs c{};
@@ -781,7 +835,8 @@ ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *st
       c.items = g->d_items;
       c.n_items = (uint32_t)g->lay.items.size();
       c.spins = g->d_spins + (size_t)grp * g->n_words;
-      c.out = g->d_cut + 2 * (size_t)(grp * g->L + j);
+      c.bias = g->has_field ? g->d_bias : nullptr;
+      c.out = g->d_cut + kCutStride * (size_t)(grp * g->L + j);
       c.bit = j;
       if (c.n_items > 0) HIP_TRY(launch_cut(g->L, g->lay.enc, c, st), "cut launch");
     }
@@ -789,7 +844,7 @@ ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *st
     HIP_TRY(launch_cut_finalize(g->d_cut, g->R, cut, energy, st), "cut finalize");
     return ISING_OK;
   }
-  std::vector<unsigned long long> sums(2 * (size_t)g->R);
+  std::vector<unsigned long long> sums(kCutStride * (size_t)g->R);
   HIP_TRY(hipMemcpyAsync(sums.data(), g->d_cut, sizeof(unsigned long long) * sums.size(), hipMemcpyDeviceToHost, st),
           "cut readback");
   {
@@ -797,12 +852,13 @@ ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *st
     if (r != ISING_OK) return r;
   }
   for (int32_t i = 0; i < g->R; ++i) {
-    const int64_t e_dir = (int64_t)sums[2 * i], c_dir = (int64_t)sums[2 * i + 1];
+    const unsigned long long *p = sums.data() + (size_t)kCutStride * i;
+    const int64_t e_dir = (int64_t)p[0], c_dir = (int64_t)p[1], F = (int64_t)p[2];
     if ((e_dir & 1) || (c_dir & 1)) return fail(ISING_ERR_DEVICE, "cut sums over directed edges are odd");
     const int64_t E = e_dir / 2, C = c_dir / 2;
     if (2 * C != g->W - E) return fail(ISING_ERR_DEVICE, "cut/energy identity 2 cut = W - E failed");
     cut[i] = C;
-    if (energy) energy[i] = E;
+    if (energy) energy[i] = E + F;
   }
   return ISING_OK;
 }

@@ -243,6 +243,7 @@ struct Fetched {
   uint4 e[KM];
   uint32_t w[KW];  // separate weights (kEncWide only)
   int32_t vid;
+  int32_t bias;    // 2 (-h) + odd-degree bit of this lane's row (external field), 0 without one
   uint32_t ownw;   // the coherent spin word holding this lane's row
   uint32_t flipw;  // stored flip bits of this sweep (sweeps not divisible by 4)
 };
@@ -258,6 +259,7 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
   const uint32_t r = (uint32_t)lane >> gs, gl = (uint32_t)lane & (G - 1u);
   const uint32_t slot = it.id + r;
   f.vid = plane < 0 ? a.vid[slot] : 0;  // the caller id only keys the Philox draws
+  f.bias = a.bias != nullptr ? a.bias[slot] : 0;
   f.ownw = ld_coherent(a.spins + ((slot * L) >> 5));
   f.flipw = plane >= 0 ? ld_coherent(a.flips + (size_t)plane * a.n_words + ((slot * L) >> 5)) : 0u;
   // the item's block starts at a wave-uniform address; offsets inside it fit 32 bits
@@ -333,6 +335,18 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   const int32_t base = ENC == kEncPm1 ? (int32_t)(it.len4 * 4u) : sw;
 #pragma unroll
   for (int j = 0; j < L; ++j) h[j] = 2 * h[j] - base;
+  // An external field h enters as -h (the spin follows the sign of
+  // h - sum w s).  With +-1 weights a row of odd degree also holds one
+  // unpaired pad, which added the row's own spin (+1 or -1) to the count
+  // form above; without a field that never changed a decision (the field
+  // is odd, hence nonzero), with one it could, so it is taken out here.
+  if (a.bias != nullptr) {
+    const int32_t hb = f.bias >> 1;
+    const uint32_t odd = ENC == kEncPm1 ? (uint32_t)f.bias & 1u : 0u;
+    const uint32_t own_bits = (f.ownw >> ((slot * L) & 31u)) & lmask<L>();
+#pragma unroll
+    for (int j = 0; j < L; ++j) h[j] += hb - (odd ? (int32_t)(((own_bits >> j) & 1u) << 1) - 1 : 0);
+  }
   const uint32_t bit0 = slot * L;
   const uint32_t sh = bit0 & 31;
   const uint32_t own = (f.ownw >> sh) & lmask<L>();
@@ -732,8 +746,9 @@ __global__ void k_check_spins(const int8_t *src, int64_t count, uint32_t *flag) 
 
 __global__ void k_cut_finalize(const unsigned long long *sums, int32_t R, int64_t *cut, int64_t *energy) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < R; i += gridDim.x * blockDim.x) {
-    cut[i] = (int64_t)sums[2 * i + 1] / 2;
-    if (energy != nullptr) energy[i] = (int64_t)sums[2 * i] / 2;
+    const unsigned long long *p = sums + (size_t)kCutStride * i;
+    cut[i] = (int64_t)p[1] / 2;
+    if (energy != nullptr) energy[i] = (int64_t)p[0] / 2 + (int64_t)p[2];
   }
 }
 
@@ -750,13 +765,15 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const uint32_t n_waves = gridDim.x * blockDim.x / kWave;
-  long long e_sum = 0, c_sum = 0;
+  long long e_sum = 0, c_sum = 0, f_sum = 0;
   for (uint32_t i = wave; i < a.n_items; i += n_waves) {
     const Item it = ro_item(a.items, i);
     const uint32_t G = it.g, K = 64u / G;
     const uint32_t r = (uint32_t)lane / G, gl = (uint32_t)lane & (G - 1u);
     const uint32_t slot = it.id + r;
     const uint32_t own = (mask_of<L>(a.spins, slot) >> a.bit) & 1u;
+    // external field energy -h s, once per row (padding rows carry 0)
+    if (a.bias != nullptr && gl == 0u) f_sum += (long long)(a.bias[slot] >> 1) * (own ? 1 : -1);
     int32_t e_part = 0, c_part = 0;
     for (uint32_t q = gl; q < it.len4; q += G) {
       const size_t c = (size_t)it.base4 + (size_t)q * K + r;
@@ -789,15 +806,17 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs a) {
   }
   e_sum = wave_sum(e_sum);
   c_sum = wave_sum(c_sum);
-  __shared__ long long s_e[4], s_c[4];
+  f_sum = wave_sum(f_sum);
+  __shared__ long long s_e[4], s_c[4], s_f[4];
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  if (lane == 0) { s_e[wib] = e_sum; s_c[wib] = c_sum; }
+  if (lane == 0) { s_e[wib] = e_sum; s_c[wib] = c_sum; s_f[wib] = f_sum; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    long long te = 0, tc = 0;
-    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) { te += s_e[i]; tc += s_c[i]; }
+    long long te = 0, tc = 0, tf = 0;
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) { te += s_e[i]; tc += s_c[i]; tf += s_f[i]; }
     atomicAdd(a.out, (unsigned long long)te);
     atomicAdd(a.out + 1, (unsigned long long)tc);
+    if (tf != 0) atomicAdd(a.out + 2, (unsigned long long)tf);
   }
 }
 

@@ -67,6 +67,8 @@ struct AnnealArgs {
   const uint4 *entries;      // edge stream, uint4 chunks
   const uint32_t *wts4;      // 4 int8 weights per chunk (general weights only)
   const int32_t *vid;        // slot -> caller vertex id, -1 for padding
+  const int32_t *bias;       // slot -> 2 (-h) + (degree odd, +-1 encoding) of the external
+                             // field (nullptr: no field); see kernels.hip compute()
   const Item *items;         // all items, phase by phase
   const uint32_t *wave_ptr;  // [n_phases][nw + 1] item ranges per global wavefront
   const uint32_t *cls_w64;   // [n_phases + 1] class boundaries in 64-bit words of the spin state
@@ -92,6 +94,9 @@ struct AnnealArgs {
   uint32_t r_total;          // replicas of the handle
 };
 
+// 64-bit sums per replica in the cut buffer (three used).
+constexpr int kCutStride = 4;
+
 struct CutArgs {
   const uint4 *entries;
   const uint32_t *wts4;
@@ -99,7 +104,9 @@ struct CutArgs {
   const Item *items;
   uint32_t n_items;
   const uint32_t *spins;
-  unsigned long long *out;   // [2]: sum over directed entries of w s s, of w [s != s]
+  const int32_t *bias;       // as in AnnealArgs
+  unsigned long long *out;   // [kCutStride]: over directed entries the sums of w s s and of
+                             // w [s != s], then the sum over vertices of -h s
   uint32_t bit;              // replica bit inside the mask
 };
 

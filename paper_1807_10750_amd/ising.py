@@ -36,7 +36,7 @@ SCHED_LINEAR = 0
 SCHED_EXPLICIT = 1
 
 EXPORTED = ["isingCreate", "isingRandomizeSpins", "isingSetSpins", "isingAnneal", "isingCut",
-            "isingGetSpins", "isingGetColoring", "isingTotalWeight", "isingGetInfo",
+            "isingGetSpins", "isingGetColoring", "isingTotalWeight", "isingSetField", "isingGetInfo",
             "isingDestroy", "isingLastError"]
 
 
@@ -78,6 +78,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "isingGetSpins": [P, P, P],
         "isingGetColoring": [P, P, P],
         "isingTotalWeight": [P, P],
+        "isingSetField": [P, P, P],
         "isingGetInfo": [P, ctypes.POINTER(Info)],
         "isingDestroy": [P],
     }
@@ -164,6 +165,10 @@ def isingTotalWeight(h, W):
     return _lib.isingTotalWeight(h, ctypes.byref(W))
 
 
+def isingSetField(h, field, stream=None):
+    return _lib.isingSetField(h, _ptr(field), _stream(stream))
+
+
 def isingGetInfo(h, info):
     return _lib.isingGetInfo(h, ctypes.byref(info))
 
@@ -245,6 +250,12 @@ class Graph:
         W = ctypes.c_int64()
         _check(isingTotalWeight(self._h, W), "isingTotalWeight")
         return W.value
+
+    def set_field(self, h, stream=None):
+        """External field h (int32 [n], caller ids); None removes it."""
+        if isinstance(h, np.ndarray):
+            h = np.ascontiguousarray(h, dtype=np.int32)
+        _check(isingSetField(self._h, h, stream), "isingSetField")
 
     def info(self):
         inf = Info()

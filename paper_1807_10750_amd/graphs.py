@@ -296,6 +296,27 @@ def batched_erdos_renyi(count: int, n_lo: int, n_hi: int, d_lo: float, d_hi: flo
             for n, d, s in zip(ns, ds, seeds)]
 
 
+def via_instance(rows: int, cols: int, max_vias: int = 3, seed: int = 1):
+    """Synthetic two-layer routing: merged segments on a rows x cols grid,
+    continuation edges between grid neighbours (each kept with probability
+    0.7) plus a few longer jumps, and via counts a, b ~ U{0..max_vias} per
+    edge.  Returns (n, u, v, a, b) with every unordered pair once."""
+    rng = np.random.default_rng(seed)
+    n = rows * cols
+    idx = np.arange(n).reshape(rows, cols)
+    pairs = [np.stack([idx[:, :-1].ravel(), idx[:, 1:].ravel()], 1),
+             np.stack([idx[:-1, :].ravel(), idx[1:, :].ravel()], 1)]
+    e = np.concatenate(pairs)
+    e = e[rng.random(len(e)) < 0.7]
+    jumps = rng.integers(0, n, size=(n // 10 + 1, 2))
+    jumps = jumps[jumps[:, 0] != jumps[:, 1]]
+    e = np.concatenate([e, np.sort(jumps, 1)])
+    e = np.unique(np.sort(e, 1), axis=0)
+    a = rng.integers(0, max_vias + 1, len(e))
+    b = rng.integers(0, max_vias + 1, len(e))
+    return n, e[:, 0], e[:, 1], a, b
+
+
 def random_spins(n: int, replicas: int = 1, seed: int = 0) -> np.ndarray:
     """Uniform random int8 +-1 spins, shape [replicas, n]."""
     rng = np.random.default_rng(seed)

@@ -164,6 +164,22 @@ ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *st
  * host destination synchronises the stream. */
 ising_status_t isingGetSpins(ising_graph_t g, int8_t *spins, void *stream);
 
+/* Best-of-run tracking (the paper keeps the final state; Sec. V-A suggests
+ * keeping the best one seen).  Computes the cut of every replica's current
+ * spins, writes it to cut (int64 [R], host or device, or NULL) and, for each
+ * replica whose cut exceeds its best since the spins were last randomised or
+ * set, records the new best cut and a copy of that replica's spins.  Called
+ * between chunked isingAnneal calls it yields a cut trace and the best
+ * state.  Stream-ordered; a host cut output synchronises the stream; with a
+ * device or NULL output it can be captured in a HIP graph. */
+ising_status_t isingUpdateBest(ising_graph_t g, int64_t *cut, void *stream);
+
+/* The best cut of every replica (int64 [R]) and its spins (int8 [R][n] in
+ * caller ids), host or device, either may be NULL.  ISING_ERR_INVALID_ARGUMENT
+ * if isingUpdateBest has not run since the spins were last randomised or
+ * set.  Host outputs synchronise the stream. */
+ising_status_t isingGetBest(ising_graph_t g, int64_t *best_cut, int8_t *spins, void *stream);
+
 /* Colouring used by DETERMINISTIC mode: color int32 [n] (host), colour of
  * every caller vertex; *n_colors its number of classes. */
 ising_status_t isingGetColoring(ising_graph_t g, int32_t *color, int32_t *n_colors);

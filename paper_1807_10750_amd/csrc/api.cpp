@@ -120,6 +120,14 @@ struct ising_graph_s {
   std::vector<uint32_t> degree;
   int32_t *d_bias = nullptr;
   bool has_field = false;
+  // best-of-run state (isingUpdateBest): best cut per replica, the spins it
+  // was seen with, per-group improvement masks, a scratch cut array
+  int64_t *d_best_cut = nullptr;
+  uint32_t *d_best_spins = nullptr;
+  uint32_t *d_best_mask = nullptr;
+  int64_t *d_cutvals = nullptr;
+  bool best_reset = true;  // no best recorded since the spins were last set
+  bool best_any = false;   // some update ran since
   // schedule cache
   bool thr_valid = false;
   double ps = -1, pe = -1;
@@ -146,7 +154,8 @@ void free_all(ising_graph_s *g) {
   void *bufs[] = {g->d_entries, g->d_wts4, g->d_vid, g->d_items, g->d_wave_ptr[0], g->d_wave_ptr[1],
                   g->d_cls_w64[0], g->d_cls_w64[1], g->d_own_w64[0], g->d_own_w64[1], g->d_flips,
                   g->d_local[0], g->d_local[1], g->d_bin_wave_ptr, g->d_bin_words,
-                  g->d_spins, g->d_thr, g->d_bar, g->d_cut, g->d_stage, g->d_bias};
+                  g->d_spins, g->d_thr, g->d_bar, g->d_cut, g->d_stage, g->d_bias,
+                  g->d_best_cut, g->d_best_spins, g->d_best_mask, g->d_cutvals};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (g->h_thr) (void)hipHostFree(g->h_thr);
@@ -684,6 +693,7 @@ ising_status_t isingRandomizeSpins(ising_graph_t g, uint64_t seed, void *stream)
                              (uint32_t)(grp * g->L), group_r_count(g, grp), seed, st),
             "randomize launch");
   }
+  g->best_reset = true;
   return ISING_OK;
 }
 
@@ -714,6 +724,7 @@ ising_status_t isingSetSpins(ising_graph_t g, const int8_t *spins, void *stream)
     HIP_TRY(launch_set_spins(g->L, g->d_spins + (size_t)grp * g->n_words, g->d_vid, g->n_words, src, g->n,
                              (uint32_t)(grp * g->L), group_r_count(g, grp), st),
             "set-spins launch");
+  g->best_reset = true;
   return ISING_OK;
 }
 
@@ -815,15 +826,9 @@ ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *s, uint64_t 
   return ISING_OK;
 }
 
-ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *stream) {
-  g_last_error.clear();
-  if (g == nullptr || cut == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
-  DeviceGuard guard(g->device);
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const bool dev_cut = is_device_ptr(cut);
-  const bool dev_e = energy != nullptr && is_device_ptr(energy);
-  if (energy != nullptr && dev_cut != dev_e)
-    return fail(ISING_ERR_INVALID_ARGUMENT, "cut and energy must both be host or both be device memory");
+// Per replica: the sums over directed entries of w s s and of w [s != s],
+// and the field energy, into g->d_cut (kCutStride words each).
+ising_status_t cut_sums(ising_graph_s *g, hipStream_t st) {
   HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(g->d_cut), 2 * kCutStride * (uint32_t)g->R, 0u, st),
           "cut reset");
   for (int grp = 0; grp < g->n_groups; ++grp)
@@ -840,6 +845,84 @@ ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *st
       c.bit = j;
       if (c.n_items > 0) HIP_TRY(launch_cut(g->L, g->lay.enc, c, st), "cut launch");
     }
+  return ISING_OK;
+}
+
+ising_status_t isingUpdateBest(ising_graph_t g, int64_t *cut, void *stream) {
+  g_last_error.clear();
+  if (g == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL handle");
+  DeviceGuard guard(g->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  ising_status_t r = ISING_OK;
+  if (g->d_best_cut == nullptr) {
+    if ((r = dev_alloc(&g->d_best_cut, sizeof(int64_t) * (size_t)g->R, "best cuts")) != ISING_OK) return r;
+    if ((r = dev_alloc(&g->d_best_spins, sizeof(uint32_t) * (size_t)g->n_words * g->n_groups, "best spins")) !=
+        ISING_OK)
+      return r;
+    if ((r = dev_alloc(&g->d_best_mask, sizeof(uint32_t) * (size_t)g->n_groups, "best masks")) != ISING_OK) return r;
+    if ((r = dev_alloc(&g->d_cutvals, sizeof(int64_t) * (size_t)g->R, "cut values")) != ISING_OK) return r;
+  }
+  const bool dev_out = cut != nullptr && is_device_ptr(cut);
+  if ((r = cut_sums(g, st)) != ISING_OK) return r;
+  int64_t *out = dev_out ? cut : g->d_cutvals;
+  HIP_TRY(launch_best(g->d_cut, g->R, g->L, g->best_reset ? 1 : 0, g->d_best_cut, out, g->d_best_mask, g->d_spins,
+                      g->d_best_spins, g->n_words, g->n_groups, st),
+          "best-of-run update");
+  g->best_reset = false;
+  g->best_any = true;
+  if (cut != nullptr && !dev_out) {
+    HIP_TRY(hipMemcpyAsync(cut, g->d_cutvals, sizeof(int64_t) * (size_t)g->R, hipMemcpyDeviceToHost, st),
+            "cut readback");
+    return check_flags(g, st);
+  }
+  return ISING_OK;
+}
+
+ising_status_t isingGetBest(ising_graph_t g, int64_t *best_cut, int8_t *spins, void *stream) {
+  g_last_error.clear();
+  if (g == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL handle");
+  if (!g->best_any || g->best_reset)
+    return fail(ISING_ERR_INVALID_ARGUMENT, "no best recorded since the spins were last set");
+  DeviceGuard guard(g->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  bool sync = false;
+  if (best_cut != nullptr) {
+    const bool dev = is_device_ptr(best_cut);
+    HIP_TRY(hipMemcpyAsync(best_cut, g->d_best_cut, sizeof(int64_t) * (size_t)g->R,
+                           dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st),
+            "best cut copy");
+    sync = sync || !dev;
+  }
+  if (spins != nullptr && g->n > 0) {
+    const bool dev = is_device_ptr(spins);
+    int8_t *dst = dev ? spins : g->d_stage;
+    for (int grp = 0; grp < g->n_groups; ++grp)
+      HIP_TRY(launch_get_spins(g->L, g->d_best_spins + (size_t)grp * g->n_words, g->d_vid, (uint32_t)g->lay.n_slots,
+                               dst, g->n, (uint32_t)(grp * g->L), group_r_count(g, grp), st),
+              "best spins");
+    if (!dev) {
+      HIP_TRY(hipMemcpyAsync(spins, g->d_stage, (size_t)g->n * (size_t)g->R, hipMemcpyDeviceToHost, st),
+              "best spins readback");
+      sync = true;
+    }
+  }
+  if (sync) HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  return ISING_OK;
+}
+
+ising_status_t isingCut(ising_graph_t g, int64_t *cut, int64_t *energy, void *stream) {
+  g_last_error.clear();
+  if (g == nullptr || cut == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
+  DeviceGuard guard(g->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool dev_cut = is_device_ptr(cut);
+  const bool dev_e = energy != nullptr && is_device_ptr(energy);
+  if (energy != nullptr && dev_cut != dev_e)
+    return fail(ISING_ERR_INVALID_ARGUMENT, "cut and energy must both be host or both be device memory");
+  {
+    ising_status_t r = cut_sums(g, st);
+    if (r != ISING_OK) return r;
+  }
   if (dev_cut) {
     HIP_TRY(launch_cut_finalize(g->d_cut, g->R, cut, energy, st), "cut finalize");
     return ISING_OK;

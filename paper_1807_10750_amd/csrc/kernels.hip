@@ -752,6 +752,33 @@ __global__ void k_cut_finalize(const unsigned long long *sums, int32_t R, int64_
   }
 }
 
+// Best-of-run tracking.  k_best_select compares each replica's cut with its
+// best so far (reset: no best yet), records improvements and marks the
+// improved replicas in their group's mask; k_best_merge then copies those
+// replicas' bits of the spin state into the best state.
+__global__ void k_best_select(const unsigned long long *sums, int32_t R, int32_t L, int32_t reset,
+                              int64_t *best, int64_t *cut_out, uint32_t *masks) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < R; i += gridDim.x * blockDim.x) {
+    const int64_t cut = (int64_t)sums[(size_t)kCutStride * i + 1] / 2;
+    if (cut_out != nullptr) cut_out[i] = cut;
+    if (reset || cut > best[i]) {
+      best[i] = cut;
+      atomicOr(masks + i / L, 1u << (i % L));
+    }
+  }
+}
+
+__global__ void k_best_merge(const uint32_t *spins, uint32_t *best, const uint32_t *masks, uint32_t n_words,
+                             uint32_t total, int32_t L) {
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < total; w += gridDim.x * blockDim.x) {
+    const uint32_t m = masks[w / n_words];
+    if (m == 0u) continue;
+    uint32_t pat = 0;
+    for (int32_t k = 0; k < 32; k += L) pat |= m << k;  // the replica bits of every slot in the word
+    best[w] = (best[w] & ~pat) | (spins[w] & pat);
+  }
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t count, uint32_t value) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = value;
 }
@@ -946,6 +973,17 @@ hipError_t cut_L(const CutArgs &a, int enc, hipStream_t s) {
   return hipGetLastError();
 }
 }  // namespace
+
+hipError_t launch_best(const unsigned long long *sums, int32_t R, int32_t L, int32_t reset, int64_t *best,
+                       int64_t *cut_out, uint32_t *masks, const uint32_t *spins, uint32_t *best_spins,
+                       uint32_t n_words, int32_t n_groups, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, masks, (uint32_t)n_groups, 0u);
+  hipLaunchKernelGGL(k_best_select, dim3((R + 255) / 256), dim3(256), 0, s, sums, R, L, reset, best, cut_out, masks);
+  const uint32_t total = n_words * (uint32_t)n_groups;
+  const int grid = (int)std::min<uint32_t>(4096u, (total + 255u) / 256u + 1u);
+  hipLaunchKernelGGL(k_best_merge, dim3(grid), dim3(256), 0, s, spins, best_spins, masks, n_words, total, L);
+  return hipGetLastError();
+}
 
 hipError_t launch_anneal(int L, int enc, bool use_lds, const AnnealArgs &a, int grid, size_t lds_bytes,
                          hipStream_t s) {

@@ -36,7 +36,8 @@ SCHED_LINEAR = 0
 SCHED_EXPLICIT = 1
 
 EXPORTED = ["isingCreate", "isingRandomizeSpins", "isingSetSpins", "isingAnneal", "isingCut",
-            "isingGetSpins", "isingGetColoring", "isingTotalWeight", "isingSetField", "isingGetInfo",
+            "isingGetSpins", "isingUpdateBest", "isingGetBest", "isingGetColoring", "isingTotalWeight",
+            "isingSetField", "isingGetInfo",
             "isingDestroy", "isingLastError"]
 
 
@@ -76,6 +77,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "isingAnneal": [P, ctypes.POINTER(Schedule), u64, c_int, i64, i64, P],
         "isingCut": [P, P, P, P],
         "isingGetSpins": [P, P, P],
+        "isingUpdateBest": [P, P, P],
+        "isingGetBest": [P, P, P, P],
         "isingGetColoring": [P, P, P],
         "isingTotalWeight": [P, P],
         "isingSetField": [P, P, P],
@@ -155,6 +158,14 @@ def isingCut(h, cut, energy=None, stream=None):
 
 def isingGetSpins(h, spins, stream=None):
     return _lib.isingGetSpins(h, _ptr(spins), _stream(stream))
+
+
+def isingUpdateBest(h, cut=None, stream=None):
+    return _lib.isingUpdateBest(h, _ptr(cut), _stream(stream))
+
+
+def isingGetBest(h, best_cut=None, spins=None, stream=None):
+    return _lib.isingGetBest(h, _ptr(best_cut), _ptr(spins), _stream(stream))
 
 
 def isingGetColoring(h, color, n_colors):
@@ -239,6 +250,29 @@ class Graph:
         dst = np.zeros((self.replicas, self.n), np.int8) if out is None else out
         _check(isingGetSpins(self._h, dst, stream), "isingGetSpins")
         return dst
+
+    def update_best(self, cut=None, stream=None):
+        """Cut of every replica now (into cut, or returned as numpy) and best-of-run bookkeeping."""
+        out = np.zeros(self.replicas, np.int64) if cut is None else cut
+        _check(isingUpdateBest(self._h, out, stream), "isingUpdateBest")
+        return out
+
+    def best(self, stream=None):
+        """(best cut int64 [R], its spins int8 [R, n]) as numpy arrays."""
+        c = np.zeros(self.replicas, np.int64)
+        s = np.zeros((self.replicas, self.n), np.int8)
+        _check(isingGetBest(self._h, c, s if self.n else None, stream), "isingGetBest")
+        return c, s
+
+    def anneal_traced(self, schedule, seed, mode=MODE_DETERMINISTIC, every=100, stream=None):
+        """Whole schedule in chunks of every sweeps; returns the cut trace
+        int64 [chunks, R] (cut after each chunk) and updates the best-of-run."""
+        M = schedule.n_sweeps
+        rows = []
+        for t0 in range(0, M, every):
+            self.anneal(schedule, seed, mode, t0, min(M, t0 + every), stream)
+            rows.append(self.update_best(stream=stream))
+        return np.stack(rows) if rows else np.zeros((0, self.replicas), np.int64)
 
     def coloring(self):
         col = np.zeros(max(self.n, 1), np.int32)

@@ -39,6 +39,17 @@ def test_binding_uses_the_c_names():
         assert hasattr(ising, n) or n == "isingLastError"
 
 
+def test_warm_start_header_symbols_are_exported():
+    text = open(os.path.join(ROOT, "include", "ising_warm.h")).read()
+    names = sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(isingWarm[A-Za-z]+)\s*\(", text, re.M)))
+    assert names == ["isingWarmAggregate", "isingWarmLastError"]
+    lib = ctypes.CDLL(_lib_path())
+    assert all(hasattr(lib, n) for n in names)
+    lib.isingWarmAggregate.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 5 + [ctypes.c_int32, ctypes.c_void_p]
+    assert lib.isingWarmAggregate(-1, None, None, None, None, None, 64, None) == 1
+    assert lib.isingWarmAggregate(0, None, None, None, None, None, 64, None) == 0
+
+
 def test_last_error_is_empty_string_initially():
     lib = ctypes.CDLL(_lib_path())
     lib.isingLastError.restype = ctypes.c_char_p

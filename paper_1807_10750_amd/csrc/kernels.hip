@@ -583,7 +583,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           ita = ro_item(a.items, ib);
           fetch<L, ENC>(a, ita, lane, fa, next_plane);
         }
-        if (USE_LDS) {
+        if (USE_LDS && (uint64_t)t % a.async_refresh == 0u) {
           const size_t oi = ((size_t)ph * gridDim.x + blockIdx.x) * 2;
           const uint32_t o0 = ro(a.own_w64, oi), o1 = ro(a.own_w64, oi + 1);
           const uint32_t b = ro(a.cls_w64, ph), e = ro(a.cls_w64, ph + 1);

@@ -88,6 +88,7 @@ struct AnnealArgs {
   uint32_t r_count;          // replicas of the group in use (<= L)
   uint32_t spin_limit;       // barrier polls before giving up (error flag)
   uint32_t async_slack;      // async: sweeps a workgroup may run ahead of the slowest one
+  uint32_t async_refresh;    // async: LDS copies refresh foreign words every this many sweeps
   // batched launch only
   const uint32_t *bin_words; // [n_bins + 1] first 32-bit spin word of each bin
   int32_t n_bins;

@@ -251,7 +251,7 @@ struct Fetched {
 // Issues every load of one item: this lane's row id, its spin word and its
 // share of the sliced-ELL chunks (chunks g, g + G, ...).
 // plane: flip plane to read for this item's sweep (-1 when the sweep draws).
-template <int L, int ENC>
+template <int L, int ENC, bool FIELD>
 __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, int lane, Fetched<L, ENC> &f, int plane) {
   const Item it = uni(it_in);
   constexpr int KM = Fetched<L, ENC>::KM;
@@ -259,7 +259,7 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
   const uint32_t r = (uint32_t)lane >> gs, gl = (uint32_t)lane & (G - 1u);
   const uint32_t slot = it.id + r;
   f.vid = plane < 0 ? a.vid[slot] : 0;  // the caller id only keys the Philox draws
-  f.bias = a.bias != nullptr ? a.bias[slot] : 0;
+  f.bias = FIELD ? a.bias[slot] : 0;
   f.ownw = ld_coherent(a.spins + ((slot * L) >> 5));
   f.flipw = plane >= 0 ? ld_coherent(a.flips + (size_t)plane * a.n_words + ((slot * L) >> 5)) : 0u;
   // the item's block starts at a wave-uniform address; offsets inside it fit 32 bits
@@ -281,7 +281,7 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
 // draws: this sweep computes the Philox blocks (t divisible by 4, or the
 // first sweep of the call); otherwise the flip bits come from the planes.
 // woff: the spin word that lds[0] holds (0 when LDS mirrors the whole state).
-template <int L, int ENC, bool USE_LDS>
+template <int L, int ENC, bool USE_LDS, bool FIELD>
 __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, int lane, const Fetched<L, ENC> &f,
                                         uint32_t *lds, uint32_t t, bool draws, uint32_t woff = 0) {
   const Item it = uni(it_in);
@@ -340,7 +340,7 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   // unpaired pad, which added the row's own spin (+1 or -1) to the count
   // form above; without a field that never changed a decision (the field
   // is odd, hence nonzero), with one it could, so it is taken out here.
-  if (a.bias != nullptr) {
+  if (FIELD) {
     const int32_t hb = f.bias >> 1;
     const uint32_t odd = ENC == kEncPm1 ? (uint32_t)f.bias & 1u : 0u;
     const uint32_t own_bits = (f.ownw >> ((slot * L) & 31u)) & lmask<L>();
@@ -429,7 +429,7 @@ __device__ __forceinline__ void restage(const AnnealArgs &a, uint32_t *lds, uint
   for (uint32_t i = b + first; i < e; i += stride) l64[i] = ld_coherent64(g64 + i);
 }
 
-template <int L, int ENC, bool USE_LDS>
+template <int L, int ENC, bool USE_LDS, bool FIELD>
 __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   // spin mirror, then the barrier verdict word
   __shared__ uint32_t mirror[USE_LDS ? kLdsBudget / 4 + 4 : 4];
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   Item ita;
   if (ib < ie) {
     ita = ro_item(a.items, ib);
-    fetch<L, ENC>(a, ita, lane, fa, plane_of(a.t_begin));
+    fetch<L, ENC, FIELD>(a, ita, lane, fa, plane_of(a.t_begin));
   }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
     const int plane = plane_of(t);
@@ -477,30 +477,30 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         Item itb, itc, pre;
         if (ib + 1 < ie) {
           itb = ro_item(a.items, ib + 1);
-          fetch<L, ENC>(a, itb, lane, fb, plane);
+          fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
         }
         if (ib + 2 < ie) pre = ro_item(a.items, ib + 2);
         for (uint32_t i = ib; i < ie; i += 3) {
           if (i + 2 < ie) {
             itc = pre;
-            fetch<L, ENC>(a, itc, lane, fc, plane);
+            fetch<L, ENC, FIELD>(a, itc, lane, fc, plane);
             if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
-          compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
           if (i + 1 >= ie) break;
           if (i + 3 < ie) {
             ita = pre;
-            fetch<L, ENC>(a, ita, lane, fa, plane);
+            fetch<L, ENC, FIELD>(a, ita, lane, fa, plane);
             if (i + 4 < ie) pre = ro_item(a.items, i + 4);
           }
-          compute<L, ENC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0);
           if (i + 2 >= ie) break;
           if (i + 4 < ie) {
             itb = pre;
-            fetch<L, ENC>(a, itb, lane, fb, plane);
+            fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
             if (i + 5 < ie) pre = ro_item(a.items, i + 5);
           }
-          compute<L, ENC, USE_LDS>(a, itc, lane, fc, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD>(a, itc, lane, fc, lds, (uint32_t)t, plane < 0);
         }
       } else if (kUnrolled) {
         // one item ahead: fa, fb in rotation
@@ -509,17 +509,17 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         for (uint32_t i = ib; i < ie; i += 2) {
           if (i + 1 < ie) {
             itb = pre;
-            fetch<L, ENC>(a, itb, lane, fb, plane);
+            fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
             if (i + 2 < ie) pre = ro_item(a.items, i + 2);
           }
-          compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
           if (i + 1 >= ie) break;
           if (i + 2 < ie) {
             ita = pre;
-            fetch<L, ENC>(a, ita, lane, fa, plane);
+            fetch<L, ENC, FIELD>(a, ita, lane, fa, plane);
             if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
-          compute<L, ENC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0);
         }
       } else {
         // one item ahead, rolled: the copy waits for the next item's loads
@@ -528,9 +528,9 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           Item itb;
           if (more) {
             itb = ro_item(a.items, i + 1);
-            fetch<L, ENC>(a, itb, lane, fb, plane);
+            fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
           }
-          compute<L, ENC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
           if (more) {
             ita = itb;
             fa = fb;
@@ -559,14 +559,14 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           }
           if (ib < ie) {
             ita = ro_item(a.items, ib);
-            fetch<L, ENC>(a, ita, lane, fa, next_plane);
+            fetch<L, ENC, FIELD>(a, ita, lane, fa, next_plane);
           }
           continue;
         }
         bar_arrive(a.bar, fenced);
         if (ib < ie) {
           ita = ro_item(a.items, ib);
-          fetch<L, ENC>(a, ita, lane, fa, next_plane);
+          fetch<L, ENC, FIELD>(a, ita, lane, fa, next_plane);
         }
         ++epoch;
         if (!bar_wait(a.bar, epoch * n_grp, a.spin_limit, fenced, s_ok)) return;
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         // only this workgroup writes (its LDS copy of those is the freshest).
         if (ib < ie) {
           ita = ro_item(a.items, ib);
-          fetch<L, ENC>(a, ita, lane, fa, next_plane);
+          fetch<L, ENC, FIELD>(a, ita, lane, fa, next_plane);
         }
         if (USE_LDS && (uint64_t)t % a.async_refresh == 0u) {
           const size_t oi = ((size_t)ph * gridDim.x + blockIdx.x) * 2;
@@ -609,7 +609,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         // one workgroup: its LDS copy is current
         if (ib < ie) {
           ita = ro_item(a.items, ib);
-          fetch<L, ENC>(a, ita, lane, fa, next_plane);
+          fetch<L, ENC, FIELD>(a, ita, lane, fa, next_plane);
         }
         if (!a.async_mode || last_phase) {
           if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -628,7 +628,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
 // need only workgroup syncs, and workgroups never wait for each other.  The
 // result equals the single-launch anneal of the union graph.
 // ---------------------------------------------------------------------------
-template <int L, int ENC, int W>
+template <int L, int ENC, int W, bool FIELD>
 __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   extern __shared__ uint32_t lds[];
   const int lane = threadIdx.x & (kWave - 1);
@@ -651,7 +651,7 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   Item ita;
   if (ib < ie) {
     ita = ro_item(a.items, ib);
-    fetch<L, ENC>(a, ita, lane, fa, plane_of(a.t_begin));
+    fetch<L, ENC, FIELD>(a, ita, lane, fa, plane_of(a.t_begin));
   }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
     const int plane = plane_of(t);
@@ -661,15 +661,15 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
       for (uint32_t i = ib; i < ie; i += 2) {
         if (i + 1 < ie) {
           itb = ro_item(a.items, i + 1);
-          fetch<L, ENC>(a, itb, lane, fb, plane);
+          fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
         }
-        compute<L, ENC, true>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, w0);
+        compute<L, ENC, true, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, w0);
         if (i + 1 >= ie) break;
         if (i + 2 < ie) {
           ita = ro_item(a.items, i + 2);
-          fetch<L, ENC>(a, ita, lane, fa, plane);
+          fetch<L, ENC, FIELD>(a, ita, lane, fa, plane);
         }
-        compute<L, ENC, true>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, w0);
+        compute<L, ENC, true, FIELD>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, w0);
       }
       const bool last_phase = ph + 1 == a.n_phases;
       const int32_t nph = last_phase ? 0 : ph + 1;
@@ -679,7 +679,7 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
       if (done) ie = ib;
       if (ib < ie) {
         ita = ro_item(a.items, ib);
-        fetch<L, ENC>(a, ita, lane, fa, last_phase ? plane_of(t + 1) : plane);
+        fetch<L, ENC, FIELD>(a, ita, lane, fa, last_phase ? plane_of(t + 1) : plane);
       }
       if (!a.async_mode || last_phase) __syncthreads();
     }
@@ -853,9 +853,9 @@ hipError_t set_lds_limit(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int L, int ENC, bool USE_LDS>
+template <int L, int ENC, bool USE_LDS, bool FIELD>
 hipError_t launch_anneal_t(const AnnealArgs &a, int grid, size_t lds_bytes, hipStream_t s) {
-  auto kern = k_anneal<L, ENC, USE_LDS>;
+  auto kern = k_anneal<L, ENC, USE_LDS, FIELD>;
   if (lds_bytes > kLdsBudget) return hipErrorInvalidValue;
   AnnealArgs copy = a;
   void *args[] = {&copy};
@@ -873,21 +873,28 @@ hipError_t launch_anneal_t(const AnnealArgs &a, int grid, size_t lds_bytes, hipS
                                     args, 0u, s);
 }
 
-template <int L, int ENC, int W>
+template <int L, int ENC, int W, bool FIELD>
 hipError_t launch_batch_t(const AnnealArgs &a, int grid, size_t lds_bytes, hipStream_t s) {
-  auto kern = k_anneal_batch<L, ENC, W>;
+  auto kern = k_anneal_batch<L, ENC, W, FIELD>;
   hipError_t e = set_lds_limit(kern, lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(W * kWave), (unsigned)lds_bytes, s, a);
   return hipGetLastError();
 }
 
+// Co-resident workgroups per CU: the lower of the variants with and
+// without an external field, so one grid size fits either launch.
 template <int L, int ENC, bool USE_LDS>
 hipError_t occupancy_t(int *blocks, size_t lds_bytes) {
-  auto kern = k_anneal<L, ENC, USE_LDS>;
   if (lds_bytes > kLdsBudget) return hipErrorInvalidValue;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, reinterpret_cast<const void *>(kern),
-                                                      kAnnealBlock, 0);
+  int b0 = 0, b1 = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &b0, reinterpret_cast<const void *>(k_anneal<L, ENC, USE_LDS, false>), kAnnealBlock, 0);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &b1, reinterpret_cast<const void *>(k_anneal<L, ENC, USE_LDS, true>), kAnnealBlock, 0);
+  *blocks = b0 < b1 ? b0 : b1;
+  return e;
 }
 
 }  // namespace
@@ -906,7 +913,11 @@ hipError_t occupancy_t(int *blocks, size_t lds_bytes) {
 namespace {
 template <int L, int ENC>
 hipError_t anneal_LE(const AnnealArgs &a, bool use_lds, int grid, size_t lds, hipStream_t s) {
-  return use_lds ? launch_anneal_t<L, ENC, true>(a, grid, lds, s) : launch_anneal_t<L, ENC, false>(a, grid, lds, s);
+  if (a.bias != nullptr)
+    return use_lds ? launch_anneal_t<L, ENC, true, true>(a, grid, lds, s)
+                   : launch_anneal_t<L, ENC, false, true>(a, grid, lds, s);
+  return use_lds ? launch_anneal_t<L, ENC, true, false>(a, grid, lds, s)
+                 : launch_anneal_t<L, ENC, false, false>(a, grid, lds, s);
 }
 template <int L>
 hipError_t anneal_L(const AnnealArgs &a, int enc, bool use_lds, int grid, size_t lds, hipStream_t s) {
@@ -916,10 +927,12 @@ hipError_t anneal_L(const AnnealArgs &a, int enc, bool use_lds, int grid, size_t
 }
 template <int L, int ENC>
 hipError_t batch_LE(const AnnealArgs &a, int waves, int grid, size_t lds, hipStream_t s) {
+  const bool f = a.bias != nullptr;
   switch (waves) {
-    case 4: return launch_batch_t<L, ENC, 4>(a, grid, lds, s);
-    case 8: return launch_batch_t<L, ENC, 8>(a, grid, lds, s);
-    case 16: return launch_batch_t<L, ENC, 16>(a, grid, lds, s);
+    case 4: return f ? launch_batch_t<L, ENC, 4, true>(a, grid, lds, s) : launch_batch_t<L, ENC, 4, false>(a, grid, lds, s);
+    case 8: return f ? launch_batch_t<L, ENC, 8, true>(a, grid, lds, s) : launch_batch_t<L, ENC, 8, false>(a, grid, lds, s);
+    case 16:
+      return f ? launch_batch_t<L, ENC, 16, true>(a, grid, lds, s) : launch_batch_t<L, ENC, 16, false>(a, grid, lds, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -197,25 +197,56 @@ __device__ __forceinline__ T wave_sum(T x) {
 // used.  A poll limit bounds the wait; hitting it raises the error flag and
 // every workgroup leaves the kernel.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void bar_arrive(uint32_t *bar, bool fenced) {
+// Barrier epochs count from 1.  Counter tree: epoch k is complete when the
+// top counter reaches k * (number of groups).  Flags: workgroup b stores k in
+// its own word when it arrives, and thread t of every workgroup waits for
+// word t; one store and one load apart instead of three dependent atomics.
+__device__ __forceinline__ void bar_arrive(const AnnealArgs &a, bool fenced, uint32_t epoch) {
   if (fenced)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   else
     __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t grp = blockIdx.x & 7u;
-    const uint32_t gsize = (gridDim.x - grp + 7u) / 8u;
-    const uint32_t old = __hip_atomic_fetch_add(bar + kBarGroup + 16 * grp, 1u, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    if ((old + 1u) % gsize == 0u)
-      __hip_atomic_fetch_add(bar + kBarTop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (a.bar_flags) {
+      st_coherent(a.bar + kBarFlags + blockIdx.x, epoch);
+    } else {
+      const uint32_t grp = blockIdx.x & 7u;
+      const uint32_t gsize = (gridDim.x - grp + 7u) / 8u;
+      const uint32_t old = __hip_atomic_fetch_add(a.bar + kBarGroup + 16 * grp, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+      if ((old + 1u) % gsize == 0u)
+        __hip_atomic_fetch_add(a.bar + kBarTop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
+// Waits until every workgroup has arrived at barrier epoch `epoch`.
 // s_ok: one LDS word of the workgroup that carries the verdict to every thread.
-__device__ __forceinline__ bool bar_wait(uint32_t *bar, uint32_t target, uint32_t limit, bool fenced,
-                                         uint32_t &s_ok) {
+__device__ __forceinline__ bool bar_wait(const AnnealArgs &a, uint32_t epoch, bool fenced, uint32_t &s_ok) {
+  uint32_t *bar = a.bar;
+  const uint32_t limit = a.spin_limit;
+  if (a.bar_flags) {
+    if (threadIdx.x == 0) s_ok = 1u;
+    __syncthreads();
+    if (threadIdx.x < gridDim.x) {
+      uint32_t polls = 0;
+      while (ld_coherent(bar + kBarFlags + threadIdx.x) < epoch) {
+        if (++polls > limit ||
+            ((polls & 63u) == 0u && __hip_atomic_load(bar + kBarErr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+          __hip_atomic_store(bar + kBarErr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_ok = 0u;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    if (fenced && threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(s_ok) != 0u;  // wave-uniform, so loops stay scalar
+  }
+  const uint32_t n_grp = gridDim.x < 8u ? gridDim.x : 8u;
+  const uint32_t target = epoch * n_grp;
   if (threadIdx.x == 0) {
     uint32_t ok = 1, polls = 0;
     while (__hip_atomic_load(bar + kBarTop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -441,7 +472,6 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   const bool multi = gridDim.x > 1;
   const bool fenced = !USE_LDS;
   uint32_t &s_ok = mirror[USE_LDS ? kLdsBudget / 4 : 0];
-  const uint32_t n_grp = gridDim.x < 8u ? gridDim.x : 8u;
   // Pipeline shape that fits the registers: two items in flight (three
   // buffers), one item in flight unrolled, or one item in flight rolled.
   constexpr bool kDeep = ENC == kEncPm1 && L <= 4;
@@ -563,13 +593,13 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           }
           continue;
         }
-        bar_arrive(a.bar, fenced);
+        bar_arrive(a, fenced, epoch + 1u);
         if (ib < ie) {
           ita = ro_item(a.items, ib);
           fetch<L, ENC, FIELD>(a, ita, lane, fa, next_plane);
         }
         ++epoch;
-        if (!bar_wait(a.bar, epoch * n_grp, a.spin_limit, fenced, s_ok)) return;
+        if (!bar_wait(a, epoch, fenced, s_ok)) return;
         if (USE_LDS) {
           restage(a, lds, run_w, ro(a.cls_w64, ph + 1), threadIdx.x, blockDim.x);
           __syncthreads();
@@ -599,11 +629,9 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         if (last_phase && !done) {
           // sweeps stay within async_slack of each other: after its sweep
           // k, a workgroup waits for every workgroup's sweep k - slack
-          bar_arrive(a.bar, fenced);
+          bar_arrive(a, fenced, epoch + 1u);
           ++epoch;
-          if (epoch > a.async_slack &&
-              !bar_wait(a.bar, (epoch - a.async_slack) * n_grp, a.spin_limit, fenced, s_ok))
-            return;
+          if (epoch > a.async_slack && !bar_wait(a, epoch - a.async_slack, fenced, s_ok)) return;
         }
       } else {
         // one workgroup: its LDS copy is current

@@ -60,7 +60,9 @@ constexpr int kBarTop = 0;       // barrier epochs completed x groups
 constexpr int kBarErr = 1;       // set when a barrier poll limit is hit
 constexpr int kBarCheck = 2;     // spin-value check result
 constexpr int kBarGroup = 16;    // group counter k at kBarGroup + 16 * k, k < 8
-constexpr int kBarWords = 256;
+constexpr int kBarFlags = 256;   // flag barrier: the epoch workgroup b reached, at kBarFlags + b
+constexpr int kBarMaxGrid = 1024;
+constexpr int kBarWords = kBarFlags + kBarMaxGrid;
 
 // Arguments of the anneal kernel (passed by value).
 struct AnnealArgs {
@@ -87,6 +89,7 @@ struct AnnealArgs {
   uint32_t r0;               // replica index of bit 0
   uint32_t r_count;          // replicas of the group in use (<= L)
   uint32_t spin_limit;       // barrier polls before giving up (error flag)
+  uint32_t bar_flags;        // 1: flag barrier (one word per workgroup), 0: counter tree
   uint32_t async_slack;      // async: sweeps a workgroup may run ahead of the slowest one
   uint32_t async_refresh;    // async: LDS copies refresh foreign words every this many sweeps
   // batched launch only

@@ -212,6 +212,8 @@ typedef struct {
   int64_t items;            /* wavefront work items per sweep */
   int32_t bins;             /* batched mode: workgroups per replica group, each owning whole
                                connected components (0: one cooperative launch) */
+  int32_t resident_bins;    /* batched mode: bins whose +-1 edge entries are read from HBM once
+                               and kept in LDS (2 bytes each) for the whole anneal */
 } ising_info_t;
 
 ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info);

@@ -107,6 +107,10 @@ struct ising_graph_s {
   size_t batch_lds = 0;
   uint32_t *d_bin_wave_ptr = nullptr;            // [n_bins][colours][waves + 1]
   uint32_t *d_bin_words = nullptr;               // [n_bins + 1]
+  uint32_t *d_bin_chunks = nullptr;              // [n_bins][2] entry chunk range of each bin
+  uint32_t *d_bin_list = nullptr;                // resident bins, then the others
+  int32_t n_res_bins = 0;                        // bins whose entries sit in LDS
+  size_t res_lds = 0;                            // LDS of the resident launch
   uint32_t *d_cls_w64[2] = {nullptr, nullptr};   // per mode: phase -> spin word range
   int32_t n_phases[2] = {0, 0};
   uint32_t *d_spins = nullptr;
@@ -153,7 +157,8 @@ ising_status_t dev_alloc(T **p, size_t bytes, const char *what) {
 void free_all(ising_graph_s *g) {
   void *bufs[] = {g->d_entries, g->d_wts4, g->d_vid, g->d_items, g->d_wave_ptr[0], g->d_wave_ptr[1],
                   g->d_cls_w64[0], g->d_cls_w64[1], g->d_own_w64[0], g->d_own_w64[1], g->d_flips,
-                  g->d_local[0], g->d_local[1], g->d_bin_wave_ptr, g->d_bin_words,
+                  g->d_local[0], g->d_local[1], g->d_bin_wave_ptr, g->d_bin_words, g->d_bin_chunks,
+                  g->d_bin_list,
                   g->d_spins, g->d_thr, g->d_bar, g->d_cut, g->d_stage, g->d_bias,
                   g->d_best_cut, g->d_best_spins, g->d_best_mask, g->d_cutvals};
   for (void *b : bufs)
@@ -256,6 +261,27 @@ typedef std::tuple<int32_t, int64_t, int64_t, int32_t, int32_t, int32_t, size_t>
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune_cache;
 
+// The batched anneal: one launch for the bins that hold their entries in
+// LDS, one for the others (each with the LDS it needs).  a carries every
+// argument except the bin list window.
+hipError_t launch_batch_parts(const ising_graph_s *g, AnnealArgs a, int waves, hipStream_t st) {
+  a.bin_chunks = g->d_bin_chunks;
+  a.bin_list = g->d_bin_list;
+  const int32_t n_other = g->lay.n_bins - g->n_res_bins;
+  hipError_t e = hipSuccess;
+  if (g->n_res_bins > 0) {
+    a.list_off = 0;
+    a.n_bins = g->n_res_bins;
+    e = launch_anneal_batch(g->L, g->lay.enc, true, waves, a, g->n_res_bins * g->n_groups, g->res_lds, st);
+  }
+  if (e == hipSuccess && n_other > 0) {
+    a.list_off = (uint32_t)g->n_res_bins;
+    a.n_bins = n_other;
+    e = launch_anneal_batch(g->L, g->lay.enc, false, waves, a, n_other * g->n_groups, g->batch_lds, st);
+  }
+  return e;
+}
+
 // Times a short deterministic anneal of the handle with each candidate wave
 // table and returns the index of the fastest.  The spins and flip planes
 // are clobbered; the caller resets them.
@@ -301,8 +327,7 @@ ising_status_t time_batch_shapes(ising_graph_s *g, const std::vector<std::vector
     // the first launch warms caches and code; the second is timed
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
       if (rep == 1) e = hipEventRecord(e0, st);
-      if (e == hipSuccess)
-        e = launch_anneal_batch(g->L, g->lay.enc, waves[c], a, g->lay.n_bins * g->n_groups, g->batch_lds, st);
+      if (e == hipSuccess) e = launch_batch_parts(g, a, waves[c], st);
       if (rep == 1 && e == hipSuccess) e = hipEventRecord(e1, st);
     }
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -490,7 +515,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   // tuner below keeps one of them
   static const int kWaveChoices[3] = {4, 8, 16};
   std::vector<std::vector<uint32_t>> bin_wave_ptrs;
-  std::vector<uint32_t> bin_words;
+  std::vector<uint32_t> bin_words, bin_chunks, bin_list;
   int tune_forced = 0;
   if (g->batch) {
     tune_forced = (int)env_int("ISING_BATCH_WAVES", 0);
@@ -514,7 +539,41 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
       max_words = std::max<size_t>(max_words, (size_t)(end - bin_words[b]));
     }
     bin_words[n_bins] = (uint32_t)((uint64_t)lay.n_slots * L / 32);
-    g->batch_lds = std::max<size_t>(max_words * 4, 16);
+    // bins whose +-1 entries fit LDS as 2-byte bin-local entries keep them
+    // there for the whole anneal; the rest stream them from HBM each sweep
+    const bool allow_res = lay.enc == kEncPm1 && env_int("ISING_BATCH_RESIDENT", 0) != 0;
+    const uint64_t res_cap = (uint64_t)std::min<int64_t>(kResidentLds, std::max<int64_t>(4096, 1024 * env_int("ISING_RESIDENT_KB", 152)));
+    std::vector<uint32_t> res, other;
+    bin_chunks.assign(2 * (size_t)n_bins, 0u);
+    size_t other_words = 0;
+    g->res_lds = 0;
+    for (int32_t b = 0; b < n_bins; ++b) {
+      const uint32_t i0 = lay.phase_items[(size_t)b * nc], i1 = lay.phase_items[(size_t)(b + 1) * nc];
+      uint64_t c0 = ~0ull, c1 = 0;
+      for (uint32_t i = i0; i < i1; ++i) {
+        const Item &it = lay.items[i];
+        c0 = std::min<uint64_t>(c0, it.base4);
+        c1 = std::max<uint64_t>(c1, (uint64_t)it.base4 + (uint64_t)it.len4 * (64u / it.g));
+      }
+      if (i0 == i1) c0 = c1 = 0;
+      bin_chunks[2 * (size_t)b] = (uint32_t)c0;
+      bin_chunks[2 * (size_t)b + 1] = (uint32_t)c1;
+      const uint64_t words = bin_words[b + 1] - bin_words[b];
+      const uint64_t slots = (uint64_t)(lay.cls_begin[(size_t)(b + 1) * nc] - lay.cls_begin[(size_t)b * nc]);
+      const uint64_t need = ((words + 1) & ~1ull) * 4 + (c1 - c0) * 8;
+      if (allow_res && slots <= kResidentMaxSlots && need <= res_cap) {
+        res.push_back((uint32_t)b);
+        g->res_lds = std::max<size_t>(g->res_lds, (size_t)need);
+      } else {
+        other.push_back((uint32_t)b);
+        other_words = std::max<size_t>(other_words, (size_t)words);
+      }
+    }
+    g->n_res_bins = (int32_t)res.size();
+    bin_list = res;
+    bin_list.insert(bin_list.end(), other.begin(), other.end());
+    g->res_lds = std::max<size_t>(g->res_lds, 16);
+    g->batch_lds = std::max<size_t>(other_words * 4, 16);
   }
 
   // device buffers
@@ -554,6 +613,14 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
     if ((r = dev_alloc(&g->d_bin_words, sizeof(uint32_t) * bin_words.size(), "bin word table")) != ISING_OK) return bail(r);
     if ((r = upload(g->d_bin_words, bin_words.data(), sizeof(uint32_t) * bin_words.size(), "bin word upload")) != ISING_OK)
       return bail(r);
+    if ((r = dev_alloc(&g->d_bin_chunks, sizeof(uint32_t) * bin_chunks.size(), "bin chunk table")) != ISING_OK)
+      return bail(r);
+    if ((r = upload(g->d_bin_chunks, bin_chunks.data(), sizeof(uint32_t) * bin_chunks.size(), "bin chunk upload")) !=
+        ISING_OK)
+      return bail(r);
+    if ((r = dev_alloc(&g->d_bin_list, sizeof(uint32_t) * bin_list.size(), "bin list")) != ISING_OK) return bail(r);
+    if ((r = upload(g->d_bin_list, bin_list.data(), sizeof(uint32_t) * bin_list.size(), "bin list upload")) != ISING_OK)
+      return bail(r);
   }
   if ((r = dev_alloc(&g->d_bar, sizeof(uint32_t) * kBarWords, "flags")) != ISING_OK) return bail(r);
   if ((r = dev_alloc(&g->d_cut, sizeof(unsigned long long) * kCutStride * (size_t)n_replicas, "cut")) != ISING_OK)
@@ -566,7 +633,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
       if (kWaveChoices[k] == tune_forced) pick = k;
     if (tune_forced == 0) {
       const TuneKey key{g->lay.n_bins, (int64_t)lay.items.size(), (int64_t)lay.n_slots, g->L, g->n_groups,
-                        lay.enc, g->batch_lds};
+                        lay.enc + 4 * g->n_res_bins, g->batch_lds + (g->res_lds << 20)};
       bool cached = false;
       {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -624,6 +691,7 @@ ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info) {
   info->grid = g->batch ? g->lay.n_bins * g->n_groups : g->grid;
   info->block = g->batch ? 64 * g->batch_waves : kAnnealBlock;
   info->bins = g->batch ? g->lay.n_bins : 0;
+  info->resident_bins = g->batch ? g->n_res_bins : 0;
   info->pm1 = g->lay.enc == kEncPm1 ? 1 : 0;
   info->encoding = g->lay.enc;
   info->edge_bytes = g->entry_bytes;
@@ -804,8 +872,7 @@ ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *s, uint64_t 
     a.r_total = (uint32_t)g->R;
     a.t_begin = sweep_begin;
     a.t_end = sweep_end;
-    HIP_TRY(launch_anneal_batch(g->L, g->lay.enc, g->batch_waves, a, g->lay.n_bins * g->n_groups, g->batch_lds, st),
-            "batched anneal launch");
+    HIP_TRY(launch_batch_parts(g, a, g->batch_waves, st), "batched anneal launch");
     return ISING_OK;
   }
   // keep the barrier counter below 2^31 within one launch

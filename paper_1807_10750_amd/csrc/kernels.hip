@@ -127,6 +127,28 @@ __device__ __forceinline__ void accumulate(int32_t (&c)[L], int32_t &sw, uint32_
   }
 }
 
+// A bin-local entry in the low 16 bits of x (the LDS copy of a resident
+// bin's spins starts at its first slot, so the slot indexes it directly).
+template <int L, typename P>
+__device__ __forceinline__ void accumulate_local(int32_t (&c)[L], uint32_t x, P words) {
+  const uint32_t slot = x & 0x7FFFu;
+  const uint32_t word = words[(slot * L) >> 5];
+  const uint32_t m = L == 1 ? word : word >> ((slot * L) & 31u);
+  const uint32_t off0 = L == 1 ? x : 0u;  // bits [4:0] of x are slot bits [4:0]
+  const uint32_t neg = (x >> 15) & 1u;
+#pragma unroll
+  for (int j = 0; j < L; ++j) c[j] += (int32_t)(__builtin_amdgcn_ubfe(m, off0 + (uint32_t)j, 1u) ^ neg);
+}
+
+template <int L, int ENC, typename P>
+__device__ __forceinline__ void accumulate4(int32_t (&c)[L], int32_t &, const uint2 &x, uint32_t, P words,
+                                            uint32_t) {
+  accumulate_local<L>(c, x.x, words);
+  accumulate_local<L>(c, x.x >> 16, words);
+  accumulate_local<L>(c, x.y, words);
+  accumulate_local<L>(c, x.y >> 16, words);
+}
+
 template <int L, int ENC, typename P>
 __device__ __forceinline__ void accumulate4(int32_t (&c)[L], int32_t &sw, const uint4 &x, uint32_t wv, P words,
                                             uint32_t woff) {
@@ -267,11 +289,21 @@ __device__ __forceinline__ bool bar_wait(const AnnealArgs &a, uint32_t epoch, bo
 // ---------------------------------------------------------------------------
 // Anneal kernel
 // ---------------------------------------------------------------------------
+// One sliced-ELL chunk: four 4-byte entries, or four 2-byte bin-local ones.
+template <int ENC>
+struct ChunkOf {
+  typedef uint4 type;
+};
+template <>
+struct ChunkOf<kEncPm1Local> {
+  typedef uint2 type;
+};
+
 template <int L, int ENC>
 struct Fetched {
   static constexpr int KM = kmax_for(L, ENC);
   static constexpr int KW = ENC == kEncWide ? KM : 1;
-  uint4 e[KM];
+  typename ChunkOf<ENC>::type e[KM];
   uint32_t w[KW];  // separate weights (kEncWide only)
   int32_t vid;
   int32_t bias;    // 2 (-h) + odd-degree bit of this lane's row (external field), 0 without one
@@ -283,7 +315,10 @@ struct Fetched {
 // share of the sliced-ELL chunks (chunks g, g + G, ...).
 // plane: flip plane to read for this item's sweep (-1 when the sweep draws).
 template <int L, int ENC, bool FIELD>
-__device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, int lane, Fetched<L, ENC> &f, int plane) {
+// lent, c0 (kEncPm1Local only): the bin's entries in LDS and the index of
+// their first chunk in the global stream.
+__device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, int lane, Fetched<L, ENC> &f, int plane,
+                                      const uint2 *lent = nullptr, uint32_t c0 = 0) {
   const Item it = uni(it_in);
   constexpr int KM = Fetched<L, ENC>::KM;
   const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs, K = 64u >> gs;
@@ -301,7 +336,10 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
     const uint32_t q = gl + (uint32_t)k * G;
     if (q < it.len4) {
       const uint32_t idx = (q << ks) + r;
-      f.e[k] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + idx * 16u);
+      if constexpr (ENC == kEncPm1Local)
+        f.e[k] = lent[it.base4 - c0 + idx];
+      else
+        f.e[k] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + idx * 16u);
       if (ENC == kEncWide)
         f.w[k < Fetched<L, ENC>::KW ? k : 0] =
             *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(wblk) + idx * 4u);
@@ -314,9 +352,12 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
 // woff: the spin word that lds[0] holds (0 when LDS mirrors the whole state).
 template <int L, int ENC, bool USE_LDS, bool FIELD>
 __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, int lane, const Fetched<L, ENC> &f,
-                                        uint32_t *lds, uint32_t t, bool draws, uint32_t woff = 0) {
+                                        uint32_t *lds, uint32_t t, bool draws, uint32_t woff = 0,
+                                        const uint2 *lent = nullptr, uint32_t c0 = 0) {
   const Item it = uni(it_in);
   constexpr int KM = Fetched<L, ENC>::KM;
+  constexpr bool kPm1 = ENC == kEncPm1 || ENC == kEncPm1Local;
+  typedef typename ChunkOf<ENC>::type Chunk;
   const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs, K = 64u >> gs;
   const uint32_t r = (uint32_t)lane >> gs, gl = (uint32_t)lane & (G - 1u);
   const uint32_t slot = it.id + r;
@@ -337,13 +378,16 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   const uint4 *blk = a.entries + it.base4;
   const uint32_t *wblk = ENC == kEncWide ? a.wts4 + it.base4 : nullptr;
   for (uint32_t q0 = gl + (uint32_t)KM * G; q0 < it.len4; q0 += 4u * G) {
-    uint4 x[4];
+    Chunk x[4];
     uint32_t wv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const uint32_t q = q0 + (uint32_t)k * G;
       const uint32_t idx = ((q < it.len4 ? q : q0) << ks) + r;
-      x[k] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + idx * 16u);
+      if constexpr (ENC == kEncPm1Local)
+        x[k] = lent[it.base4 - c0 + idx];
+      else
+        x[k] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + idx * 16u);
       wv[k] = ENC == kEncWide ? *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(wblk) + idx * 4u)
                               : 0u;
     }
@@ -360,10 +404,10 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   for (uint32_t off = 1; off < G; off <<= 1) {
 #pragma unroll
     for (int j = 0; j < L; ++j) h[j] += __shfl_xor(h[j], (int)off);
-    if (ENC != kEncPm1) sw += __shfl_xor(sw, (int)off);
+    if (!kPm1) sw += __shfl_xor(sw, (int)off);
   }
   // counts to fields
-  const int32_t base = ENC == kEncPm1 ? (int32_t)(it.len4 * 4u) : sw;
+  const int32_t base = kPm1 ? (int32_t)(it.len4 * 4u) : sw;
 #pragma unroll
   for (int j = 0; j < L; ++j) h[j] = 2 * h[j] - base;
   // An external field h enters as -h (the spin follows the sign of
@@ -373,7 +417,7 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   // is odd, hence nonzero), with one it could, so it is taken out here.
   if (FIELD) {
     const int32_t hb = f.bias >> 1;
-    const uint32_t odd = ENC == kEncPm1 ? (uint32_t)f.bias & 1u : 0u;
+    const uint32_t odd = kPm1 ? (uint32_t)f.bias & 1u : 0u;
     const uint32_t own_bits = (f.ownw >> ((slot * L) & 31u)) & lmask<L>();
 #pragma unroll
     for (int j = 0; j < L; ++j) h[j] += hb - (odd ? (int32_t)(((own_bits >> j) & 1u) << 1) - 1 : 0);
@@ -661,7 +705,7 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   extern __shared__ uint32_t lds[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  const uint32_t bin = blockIdx.x % (uint32_t)args.n_bins;
+  const uint32_t bin = ro(args.bin_list, args.list_off + blockIdx.x % (uint32_t)args.n_bins);
   const uint32_t grp = blockIdx.x / (uint32_t)args.n_bins;
   AnnealArgs a = args;
   a.spins = args.spins + (size_t)grp * args.n_words;
@@ -670,6 +714,24 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   a.r_count = args.r_total - a.r0 < (uint32_t)L ? args.r_total - a.r0 : (uint32_t)L;
   const uint32_t w0 = ro(args.bin_words, bin), w1 = ro(args.bin_words, bin + 1);
   for (uint32_t i = threadIdx.x; i < w1 - w0; i += blockDim.x) lds[i] = ld_coherent(a.spins + w0 + i);
+  // A resident bin reads its entries from HBM once, here, as 2-byte
+  // bin-local entries after its spin words; every sweep then reads LDS.
+  uint2 *lent = nullptr;
+  uint32_t c0 = 0;
+  if constexpr (ENC == kEncPm1Local) {
+    lent = reinterpret_cast<uint2 *>(lds + (((w1 - w0) + 1u) & ~1u));
+    c0 = ro(args.bin_chunks, 2 * (size_t)bin);
+    const uint32_t c1 = ro(args.bin_chunks, 2 * (size_t)bin + 1);
+    const uint32_t slot0 = (uint32_t)(((uint64_t)w0 * 32u) / (uint32_t)L);
+    for (uint32_t i = threadIdx.x; i < c1 - c0; i += blockDim.x) {
+      const uint4 x = args.entries[c0 + i];
+      const uint32_t e0 = ((x.x & ~kSignBit) - slot0) | ((x.x >> 31) << 15);
+      const uint32_t e1 = ((x.y & ~kSignBit) - slot0) | ((x.y >> 31) << 15);
+      const uint32_t e2 = ((x.z & ~kSignBit) - slot0) | ((x.z >> 31) << 15);
+      const uint32_t e3 = ((x.w & ~kSignBit) - slot0) | ((x.w >> 31) << 15);
+      lent[i] = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
+    }
+  }
   __syncthreads();
   if (a.n_phases <= 0 || a.t_begin >= a.t_end) return;
   auto plane_of = [&](int64_t t) -> int { return (t == a.t_begin || (t & 3) == 0) ? -1 : (int)(t & 3) - 1; };
@@ -679,7 +741,7 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   Item ita;
   if (ib < ie) {
     ita = ro_item(a.items, ib);
-    fetch<L, ENC, FIELD>(a, ita, lane, fa, plane_of(a.t_begin));
+    fetch<L, ENC, FIELD>(a, ita, lane, fa, plane_of(a.t_begin), lent, c0);
   }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
     const int plane = plane_of(t);
@@ -689,15 +751,15 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
       for (uint32_t i = ib; i < ie; i += 2) {
         if (i + 1 < ie) {
           itb = ro_item(a.items, i + 1);
-          fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
+          fetch<L, ENC, FIELD>(a, itb, lane, fb, plane, lent, c0);
         }
-        compute<L, ENC, true, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, w0);
+        compute<L, ENC, true, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, w0, lent, c0);
         if (i + 1 >= ie) break;
         if (i + 2 < ie) {
           ita = ro_item(a.items, i + 2);
-          fetch<L, ENC, FIELD>(a, ita, lane, fa, plane);
+          fetch<L, ENC, FIELD>(a, ita, lane, fa, plane, lent, c0);
         }
-        compute<L, ENC, true, FIELD>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, w0);
+        compute<L, ENC, true, FIELD>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, w0, lent, c0);
       }
       const bool last_phase = ph + 1 == a.n_phases;
       const int32_t nph = last_phase ? 0 : ph + 1;
@@ -707,7 +769,7 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
       if (done) ie = ib;
       if (ib < ie) {
         ita = ro_item(a.items, ib);
-        fetch<L, ENC, FIELD>(a, ita, lane, fa, last_phase ? plane_of(t + 1) : plane);
+        fetch<L, ENC, FIELD>(a, ita, lane, fa, last_phase ? plane_of(t + 1) : plane, lent, c0);
       }
       if (!a.async_mode || last_phase) __syncthreads();
     }
@@ -965,7 +1027,8 @@ hipError_t batch_LE(const AnnealArgs &a, int waves, int grid, size_t lds, hipStr
   }
 }
 template <int L>
-hipError_t batch_L(const AnnealArgs &a, int enc, int waves, int grid, size_t lds, hipStream_t s) {
+hipError_t batch_L(const AnnealArgs &a, int enc, bool resident, int waves, int grid, size_t lds, hipStream_t s) {
+  if (resident) return enc == kEncPm1 ? batch_LE<L, kEncPm1Local>(a, waves, grid, lds, s) : hipErrorInvalidValue;
   if (enc == kEncPm1) return batch_LE<L, kEncPm1>(a, waves, grid, lds, s);
   if (enc == kEncW8) return batch_LE<L, kEncW8>(a, waves, grid, lds, s);
   return batch_LE<L, kEncWide>(a, waves, grid, lds, s);
@@ -1031,9 +1094,9 @@ hipError_t launch_anneal(int L, int enc, bool use_lds, const AnnealArgs &a, int 
   ISING_DISPATCH_L(L, anneal_L, a, enc, use_lds, grid, lds_bytes, s);
 }
 
-hipError_t launch_anneal_batch(int L, int enc, int waves, const AnnealArgs &a, int grid, size_t lds_bytes,
-                               hipStream_t s) {
-  ISING_DISPATCH_L(L, batch_L, a, enc, waves, grid, lds_bytes, s);
+hipError_t launch_anneal_batch(int L, int enc, bool resident, int waves, const AnnealArgs &a, int grid,
+                               size_t lds_bytes, hipStream_t s) {
+  ISING_DISPATCH_L(L, batch_L, a, enc, resident, waves, grid, lds_bytes, s);
 }
 
 hipError_t anneal_occupancy(int L, int enc, bool use_lds, size_t lds_bytes, int *blocks_per_cu) {

@@ -44,8 +44,14 @@ constexpr uint32_t kSignBit = 0x80000000u;
 
 // Chunks of 4 entries each lane prefetches per item; bounds the degree of a
 // row handled with G lanes to 4 * kmax * G (longer rows loop).
-enum Encoding { kEncPm1 = 0, kEncW8 = 1, kEncWide = 2 };
+enum Encoding { kEncPm1 = 0, kEncW8 = 1, kEncWide = 2, kEncPm1Local = 3 };
+// kEncPm1Local exists only inside a batched workgroup whose bin fits LDS:
+// the bin's +-1 entries are copied there once as 2 bytes each, the slot
+// relative to the bin's first slot (15 bits) | sign << 15, two per word.
 constexpr int kmax_for(int L, int enc) { return (L >= 16 || enc == kEncWide || (enc == kEncW8 && L >= 2)) ? 2 : 4; }
+// LDS a resident bin may use for its spin words and 2-byte entries.
+constexpr uint32_t kResidentLds = 152 * 1024;
+constexpr uint32_t kResidentMaxSlots = 1u << 15;
 
 // One unit of work for one wavefront.
 struct Item {
@@ -94,7 +100,10 @@ struct AnnealArgs {
   uint32_t async_refresh;    // async: LDS copies refresh foreign words every this many sweeps
   // batched launch only
   const uint32_t *bin_words; // [n_bins + 1] first 32-bit spin word of each bin
-  int32_t n_bins;
+  const uint32_t *bin_chunks;// [n_bins][2] the bin's range of uint4 entry chunks
+  const uint32_t *bin_list;  // bins of this launch at list_off .. list_off + n_bins - 1
+  uint32_t list_off;
+  int32_t n_bins;            // bins of this launch
   uint32_t r_total;          // replicas of the handle
 };
 

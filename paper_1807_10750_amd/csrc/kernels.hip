@@ -60,6 +60,9 @@ __device__ __forceinline__ uint32_t ld_coherent(const uint32_t *p) {
 __device__ __forceinline__ unsigned long long ld_coherent64(const unsigned long long *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ uint32_t ld_workgroup(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 __device__ __forceinline__ void st_coherent(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -326,8 +329,10 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
   const uint32_t slot = it.id + r;
   f.vid = plane < 0 ? a.vid[slot] : 0;  // the caller id only keys the Philox draws
   f.bias = FIELD ? a.bias[slot] : 0;
-  f.ownw = ld_coherent(a.spins + ((slot * L) >> 5));
-  f.flipw = plane >= 0 ? ld_coherent(a.flips + (size_t)plane * a.n_words + ((slot * L) >> 5)) : 0u;
+  // Only this item (so this workgroup) writes its row's spin and flip bits,
+  // and only those bits are used: workgroup-scope loads are enough.
+  f.ownw = ld_workgroup(a.spins + ((slot * L) >> 5));
+  f.flipw = plane >= 0 ? ld_workgroup(a.flips + (size_t)plane * a.n_words + ((slot * L) >> 5)) : 0u;
   // the item's block starts at a wave-uniform address; offsets inside it fit 32 bits
   const uint4 *blk = a.entries + it.base4;
   const uint32_t *wblk = ENC == kEncWide ? a.wts4 + it.base4 : nullptr;

@@ -214,6 +214,9 @@ typedef struct {
                                connected components (0: one cooperative launch) */
   int32_t resident_bins;    /* batched mode: bins whose +-1 edge entries are read from HBM once
                                and kept in LDS (2 bytes each) for the whole anneal */
+  int32_t resident_edges;   /* cooperative launch: bit m set if mode m (0 deterministic, 1 async)
+                               reads the +-1 edge entries from HBM once per call and keeps them
+                               in registers (3 bytes each) for all its sweeps */
 } ising_info_t;
 
 ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info);

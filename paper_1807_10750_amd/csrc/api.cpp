@@ -109,6 +109,7 @@ struct ising_graph_s {
   uint32_t *d_bin_words = nullptr;               // [n_bins + 1]
   uint32_t *d_bin_chunks = nullptr;              // [n_bins][2] entry chunk range of each bin
   uint32_t *d_bin_list = nullptr;                // resident bins, then the others
+  bool res_edges[2] = {false, false};             // per mode: entries held in registers (kResChunks)
   int32_t n_res_bins = 0;                        // bins whose entries sit in LDS
   size_t res_lds = 0;                            // LDS of the resident launch
   uint32_t *d_cls_w64[2] = {nullptr, nullptr};   // per mode: phase -> spin word range
@@ -504,8 +505,15 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
     if (m == 0 && g->grid > 1)
       for (int32_t p = 0; p < g->n_phases[m]; ++p)
         local[m][p] = (int64_t)(lay.phase_items[pc[p + 1]] - lay.phase_items[pc[p]]) <= local_items ? 1u : 0u;
-    wave_ptr[m] = partition_waves(lay, pc, g->nw, local[m], waves_per_block);
+    wave_ptr[m] = partition_waves(lay, pc, g->nw, local[m], waves_per_block, true);
     own_w64[m] = own_words(lay, wave_ptr[m], g->n_phases[m], g->grid, waves_per_block, L);
+    // register-resident entries when every wavefront's items fit them
+    if (!g->batch && g->use_lds && L == 1 && lay.enc == kEncPm1 && lay.n_slots <= kResMaxSlots &&
+        env_int("ISING_RESIDENT_EDGES", 1) != 0) {
+      uint64_t items = 0;
+      const uint64_t chunks = max_wave_chunks(lay, wave_ptr[m], g->n_phases[m], g->nw, &items);
+      g->res_edges[m] = chunks <= (uint64_t)kResChunks && items <= (uint64_t)kResMaxItems;
+    }
     cls_w64[m].resize(pc.size());
     for (size_t p = 0; p < pc.size(); ++p) cls_w64[m][p] = (uint32_t)((uint64_t)lay.cls_begin[pc[p]] * L / 64);
   }
@@ -531,7 +539,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
       for (int32_t c = 0; c <= nc; ++c) pc[c] = b * nc + c;
       for (int k = 0; k < 3; ++k) {
         if (tune_forced != 0 && kWaveChoices[k] != tune_forced) continue;
-        const std::vector<uint32_t> wp = partition_waves(lay, pc, kWaveChoices[k], none, kWaveChoices[k]);
+        const std::vector<uint32_t> wp = partition_waves(lay, pc, kWaveChoices[k], none, kWaveChoices[k], false);
         bin_wave_ptrs[k].insert(bin_wave_ptrs[k].end(), wp.begin(), wp.end());
       }
       bin_words[b] = (uint32_t)((uint64_t)lay.cls_begin[(size_t)b * nc] * L / 32);
@@ -692,6 +700,7 @@ ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info) {
   info->block = g->batch ? 64 * g->batch_waves : kAnnealBlock;
   info->bins = g->batch ? g->lay.n_bins : 0;
   info->resident_bins = g->batch ? g->n_res_bins : 0;
+  info->resident_edges = (g->res_edges[0] ? 1 : 0) | (g->res_edges[1] ? 2 : 0);
   info->pm1 = g->lay.enc == kEncPm1 ? 1 : 0;
   info->encoding = g->lay.enc;
   info->edge_bytes = g->entry_bytes;
@@ -889,7 +898,8 @@ ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *s, uint64_t 
       a.t_end = std::min(sweep_end, t0 + chunk);
       HIP_TRY(launch_fill_u32(g->d_bar + kBarTop, 1, 0u, st), "barrier reset");
       HIP_TRY(launch_fill_u32(g->d_bar + kBarGroup, kBarWords - kBarGroup, 0u, st), "barrier reset");
-      HIP_TRY(launch_anneal(g->L, g->lay.enc, g->use_lds, a, g->grid, g->lds_bytes, st), "anneal launch");
+      HIP_TRY(launch_anneal(g->L, g->lay.enc, g->use_lds, g->res_edges[m], a, g->grid, g->lds_bytes, st),
+              "anneal launch");
     }
   }
   return ISING_OK;

@@ -13,9 +13,21 @@ constexpr int kAnnealBlock = 1024;  // 16 wavefronts per workgroup
 // Largest spin state the cooperative anneal mirrors in LDS (a static array
 // of the kernel: its address is a compile-time constant).
 constexpr size_t kLdsBudget = 160 * 1024 - 2048;
+// Register-resident entries (cooperative anneal, +-1 weights, one replica
+// bit per slot, LDS mirror): chunks of four entries each lane holds, three
+// registers per chunk.  Slots must fit the 23 bits of a packed entry.
+constexpr int kResChunks = 24;
+// Items per wavefront in that variant: each keeps its row spin and three
+// flip bits per lane in two registers (one bit and three bits per item).
+constexpr int kResMaxItems = 10;
+constexpr int64_t kResMaxSlots = int64_t(1) << 23;
+template <int L, int ENC, bool USE_LDS>
+constexpr bool kHasResident = L == 1 && ENC == kEncPm1 && USE_LDS;
 
-hipError_t launch_anneal(int L, int enc, bool use_lds, const AnnealArgs &a, int grid, size_t lds_bytes,
-                         hipStream_t s);
+// resident: the kResChunks variant; every wavefront's items must then hold
+// at most kResChunks chunks per lane in total (ceil(len4 / g) per item).
+hipError_t launch_anneal(int L, int enc, bool use_lds, bool resident, const AnnealArgs &a, int grid,
+                         size_t lds_bytes, hipStream_t s);
 // Batched anneal: grid = n_bins x replica groups, waves per workgroup in {4, 8, 16}.
 // resident: the bins of this launch hold their +-1 entries in LDS (kEncPm1Local).
 hipError_t launch_anneal_batch(int L, int enc, bool resident, int waves, const AnnealArgs &a, int grid,

@@ -161,6 +161,34 @@ __device__ __forceinline__ void accumulate4(int32_t (&c)[L], int32_t &sw, const 
   accumulate<L, ENC>(c, sw, x.w, (int32_t)(int8_t)(wv >> 24), words, woff);
 }
 
+// Register-resident +-1 entries: four 24-bit entries (slot in bits [22:0],
+// sign in bit 23) packed in three words, so a chunk takes three registers.
+__device__ __forceinline__ uint32_t to24(uint32_t x) { return (x & 0x7FFFFFu) | ((x >> 31) << 23); }
+__device__ __forceinline__ void pack24(const uint4 &x, uint32_t *w) {
+  const uint32_t p0 = to24(x.x), p1 = to24(x.y), p2 = to24(x.z), p3 = to24(x.w);
+  w[0] = p0 | (p1 << 24);
+  w[1] = (p1 >> 8) | (p2 << 16);
+  w[2] = (p2 >> 16) | (p3 << 8);
+}
+// One 24-bit entry in the low bits of x (bits above 23 are ignored).
+template <int L, typename P>
+__device__ __forceinline__ void accumulate24(int32_t (&c)[L], uint32_t x, P words) {
+  const uint32_t slot = x & 0x7FFFFFu;
+  const uint32_t word = words[(slot * L) >> 5];
+  const uint32_t m = L == 1 ? word : word >> ((slot * L) & 31u);
+  const uint32_t off0 = L == 1 ? x : 0u;  // bits [4:0] of x are slot bits [4:0]
+  const uint32_t neg = (x >> 23) & 1u;
+#pragma unroll
+  for (int j = 0; j < L; ++j) c[j] += (int32_t)(__builtin_amdgcn_ubfe(m, off0 + (uint32_t)j, 1u) ^ neg);
+}
+template <int L, typename P>
+__device__ __forceinline__ void accumulate_packed(int32_t (&c)[L], const uint32_t *w, P words) {
+  accumulate24<L>(c, w[0], words);
+  accumulate24<L>(c, __builtin_amdgcn_alignbit(w[1], w[0], 24), words);
+  accumulate24<L>(c, __builtin_amdgcn_alignbit(w[2], w[1], 16), words);
+  accumulate24<L>(c, w[2] >> 8, words);
+}
+
 // Local update (Eq. 2 with J = -w, a zero field keeps the spin) of every
 // replica bit, then the annealing flips (bit j set = flip replica j).
 // Padding slots have only padding entries (whose pairs cancel) and draw no flips.
@@ -317,9 +345,10 @@ struct Fetched {
 // Issues every load of one item: this lane's row id, its spin word and its
 // share of the sliced-ELL chunks (chunks g, g + G, ...).
 // plane: flip plane to read for this item's sweep (-1 when the sweep draws).
-template <int L, int ENC, bool FIELD>
 // lent, c0 (kEncPm1Local only): the bin's entries in LDS and the index of
 // their first chunk in the global stream.
+// RC > 0: the chunks are register-resident; only the row data is loaded.
+template <int L, int ENC, bool FIELD, int RC = 0>
 __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, int lane, Fetched<L, ENC> &f, int plane,
                                       const uint2 *lent = nullptr, uint32_t c0 = 0) {
   const Item it = uni(it_in);
@@ -331,13 +360,13 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
   f.bias = FIELD ? a.bias[slot] : 0;
   // Only this item (so this workgroup) writes its row's spin and flip bits,
   // and only those bits are used: workgroup-scope loads are enough.
-  f.ownw = ld_workgroup(a.spins + ((slot * L) >> 5));
-  f.flipw = plane >= 0 ? ld_workgroup(a.flips + (size_t)plane * a.n_words + ((slot * L) >> 5)) : 0u;
+  f.ownw = RC > 0 ? 0u : ld_workgroup(a.spins + ((slot * L) >> 5));
+  f.flipw = RC == 0 && plane >= 0 ? ld_workgroup(a.flips + (size_t)plane * a.n_words + ((slot * L) >> 5)) : 0u;
   // the item's block starts at a wave-uniform address; offsets inside it fit 32 bits
   const uint4 *blk = a.entries + it.base4;
   const uint32_t *wblk = ENC == kEncWide ? a.wts4 + it.base4 : nullptr;
 #pragma unroll
-  for (int k = 0; k < KM; ++k) {
+  for (int k = 0; k < (RC > 0 ? 0 : KM); ++k) {
     const uint32_t q = gl + (uint32_t)k * G;
     if (q < it.len4) {
       const uint32_t idx = (q << ks) + r;
@@ -352,13 +381,57 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
   }
 }
 
+// Per-lane state of a wavefront whose items stay the same for a whole call
+// (one replica bit per slot).  Item j of the wavefront's sweep order (all
+// phases) keeps this lane's row spin in bit j of own and the flip bits of
+// the three sweeps after a drawing sweep in bits 3j .. 3j + 2 of flip: only
+// that item writes the row, so the registers hold the current values and a
+// sweep loads no spin or flip words.  cr is the next item's first chunk
+// register, j the next item's index.
+struct ResState {
+  uint32_t cr, j, own, flip;
+};
+
+// Register-resident chunks of one item (+-1 entries): this lane's chunks
+// g, g + G, ... go to registers rw[3 cr ...] onwards, packed by pack24; cr
+// advances by the item's chunks per lane, ceil(len4 / G), which is the same
+// for every lane.  Registers of chunks past a lane's share are left as they
+// are (compute skips them by the same test).  Also loads the row's spin.
+template <int RC>
+__device__ __forceinline__ void load_resident(const AnnealArgs &a, const Item &it_in, int lane, uint32_t (&rw)[3 * RC],
+                                              ResState &rs) {
+  const Item it = uni(it_in);
+  const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs;
+  const uint32_t r = (uint32_t)lane >> gs, gl = (uint32_t)lane & (G - 1u);
+  const uint32_t nch = (it.len4 + G - 1u) >> gs;
+  const uint4 *blk = a.entries + it.base4;
+#pragma unroll
+  for (int c = 0; c < RC; ++c) {
+    const uint32_t k = (uint32_t)c - rs.cr;
+    const uint32_t q = gl + k * G;
+    if (k < nch && q < it.len4) {
+      const uint4 x = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + ((q << ks) + r) * 16u);
+      pack24(x, &rw[3 * c]);
+    }
+  }
+  const uint32_t slot = it.id + r;
+  const uint32_t ownw = ld_workgroup(a.spins + (slot >> 5));
+  rs.own |= ((ownw >> (slot & 31u)) & 1u) << rs.j;
+  rs.cr += nch;
+  rs.j += 1;
+}
+
 // draws: this sweep computes the Philox blocks (t divisible by 4, or the
 // first sweep of the call); otherwise the flip bits come from the planes.
 // woff: the spin word that lds[0] holds (0 when LDS mirrors the whole state).
-template <int L, int ENC, bool USE_LDS, bool FIELD>
+// RC > 0: the item's chunks sit in rw from chunk rs->cr on, its spin and
+// flip bits in rs (load_resident); rs moves on to the next item.
+template <int L, int ENC, bool USE_LDS, bool FIELD, int RC = 0>
 __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, int lane, const Fetched<L, ENC> &f,
                                         uint32_t *lds, uint32_t t, bool draws, uint32_t woff = 0,
-                                        const uint2 *lent = nullptr, uint32_t c0 = 0) {
+                                        const uint2 *lent = nullptr, uint32_t c0 = 0, const uint32_t *rw = nullptr,
+                                        ResState *rs = nullptr) {
+  static_assert(RC == 0 || L == 1, "resident state holds one replica bit per slot");
   const Item it = uni(it_in);
   constexpr int KM = Fetched<L, ENC>::KM;
   constexpr bool kPm1 = ENC == kEncPm1 || ENC == kEncPm1Local;
@@ -369,8 +442,24 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   int32_t h[L], sw = 0;
 #pragma unroll
   for (int j = 0; j < L; ++j) h[j] = 0;
+  if constexpr (RC > 0) {
+    const uint32_t nch = (it.len4 + G - 1u) >> gs;
+    const uint32_t cb = rs->cr;
 #pragma unroll
-  for (int k = 0; k < KM; ++k) {
+    for (int c = 0; c < RC; ++c) {
+      const uint32_t k = (uint32_t)c - cb;
+      if (k < nch && gl + k * G < it.len4) {
+        // opaque copies: without them the compiler hoists every entry's
+        // decoded address out of the sweep loop, three registers per entry
+        uint32_t x[3] = {rw[3 * c], rw[3 * c + 1], rw[3 * c + 2]};
+        asm volatile("" : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]));
+        accumulate_packed<L>(h, x, lds);
+      }
+    }
+    rs->cr = cb + nch;
+  }
+#pragma unroll
+  for (int k = 0; k < (RC > 0 ? 0 : KM); ++k) {
     if (gl + (uint32_t)k * G < it.len4) {
       const uint32_t wv = ENC == kEncWide ? f.w[k < Fetched<L, ENC>::KW ? k : 0] : 0u;
       if (USE_LDS)
@@ -382,7 +471,7 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   // rows longer than the prefetch depth: the rest of the chunks, four loads in flight
   const uint4 *blk = a.entries + it.base4;
   const uint32_t *wblk = ENC == kEncWide ? a.wts4 + it.base4 : nullptr;
-  for (uint32_t q0 = gl + (uint32_t)KM * G; q0 < it.len4; q0 += 4u * G) {
+  for (uint32_t q0 = gl + (uint32_t)KM * G; RC == 0 && q0 < it.len4; q0 += 4u * G) {
     Chunk x[4];
     uint32_t wv[4];
 #pragma unroll
@@ -423,17 +512,28 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   if (FIELD) {
     const int32_t hb = f.bias >> 1;
     const uint32_t odd = kPm1 ? (uint32_t)f.bias & 1u : 0u;
-    const uint32_t own_bits = (f.ownw >> ((slot * L) & 31u)) & lmask<L>();
+    const uint32_t own_bits = RC > 0 ? (rs->own >> rs->j) & 1u : (f.ownw >> ((slot * L) & 31u)) & lmask<L>();
 #pragma unroll
     for (int j = 0; j < L; ++j) h[j] += hb - (odd ? (int32_t)(((own_bits >> j) & 1u) << 1) - 1 : 0);
   }
   const uint32_t bit0 = slot * L;
   const uint32_t sh = bit0 & 31;
-  const uint32_t own = (f.ownw >> sh) & lmask<L>();
+  const uint32_t own = RC > 0 ? (rs->own >> rs->j) & 1u : (f.ownw >> sh) & lmask<L>();
   uint32_t later[3];
-  const uint32_t flips =
-      draws ? draw_flips<L>(f.vid, t, a, later) : ((f.flipw >> sh) & lmask<L>());
+  uint32_t flips;
+  if (draws)
+    flips = draw_flips<L>(f.vid, t, a, later);
+  else if (RC > 0)
+    flips = (rs->flip >> (3u * rs->j + (t & 3u) - 1u)) & 1u;  // sweep t's plane is (t mod 4) - 1
+  else
+    flips = (f.flipw >> sh) & lmask<L>();
   const uint32_t nm = update_mask<L>(h, own, flips);
+  if constexpr (RC > 0) {
+    const uint32_t jb = rs->j;
+    rs->own = (rs->own & ~(1u << jb)) | (nm << jb);
+    if (draws) rs->flip = (rs->flip & ~(7u << (3u * jb))) | ((later[0] | (later[1] << 1) | (later[2] << 2)) << (3u * jb));
+    rs->j = jb + 1u;
+  }
   const bool rep = gl == 0u;
   if (K * L >= 32u) {
     // the item owns whole words: plain coherent stores
@@ -443,7 +543,7 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
         st_coherent64(reinterpret_cast<unsigned long long *>(a.spins) + (it.id >> 6), b);
         if (USE_LDS) reinterpret_cast<unsigned long long *>(lds)[(it.id >> 6) - (woff >> 1)] = b;
       }
-      if (draws) {
+      if (RC == 0 && draws) {
         const uint32_t first = t & 3u;  // planes first .. 2 hold sweeps first+1 .. 3
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -461,7 +561,7 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
         st_coherent(a.spins + (bit0 >> 5), val);
         if (USE_LDS) lds[(bit0 >> 5) - woff] = val;
       }
-      if (draws) {
+      if (RC == 0 && draws) {
         const uint32_t first = t & 3u;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -480,7 +580,7 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
       __hip_atomic_fetch_xor(a.spins + (bit0 >> 5), chg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (USE_LDS) atomicXor(lds + ((bit0 >> 5) - woff), chg);
     }
-    if (draws) {
+    if (RC == 0 && draws) {
       // this item's bits of the word: clear, then set
       uint32_t span = rep ? lmask<L>() << sh : 0u;
       for (uint32_t off = G; off < 64u; off <<= 1) span |= __shfl_xor(span, (int)off);
@@ -509,8 +609,11 @@ __device__ __forceinline__ void restage(const AnnealArgs &a, uint32_t *lds, uint
   for (uint32_t i = b + first; i < e; i += stride) l64[i] = ld_coherent64(g64 + i);
 }
 
-template <int L, int ENC, bool USE_LDS, bool FIELD>
+// RC > 0: each wavefront keeps its items' +-1 entries in registers for the
+// whole call (at most RC chunks per lane), so a sweep reads no edge stream.
+template <int L, int ENC, bool USE_LDS, bool FIELD, int RC = 0>
 __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
+  static_assert(RC == 0 || (USE_LDS && ENC == kEncPm1), "resident entries need the LDS mirror and +-1 entries");
   // spin mirror, then the barrier verdict word
   __shared__ uint32_t mirror[USE_LDS ? kLdsBudget / 4 + 4 : 4];
   uint32_t *const lds = mirror;
@@ -523,28 +626,40 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   uint32_t &s_ok = mirror[USE_LDS ? kLdsBudget / 4 : 0];
   // Pipeline shape that fits the registers: two items in flight (three
   // buffers), one item in flight unrolled, or one item in flight rolled.
-  constexpr bool kDeep = ENC == kEncPm1 && L <= 4;
-  constexpr bool kUnrolled = L <= 4;
+  constexpr bool kDeep = ENC == kEncPm1 && L <= 4 && RC == 0;
+  constexpr bool kUnrolled = L <= 4 && RC == 0;
   if (USE_LDS) {
     restage(a, lds, 0, a.n_words / 2, threadIdx.x, blockDim.x);
     __syncthreads();
   }
   if (a.n_phases <= 0 || a.t_begin >= a.t_end) return;
+  const size_t stride = (size_t)a.nw + 1;
+  // resident chunks of this wavefront's items, phase by phase in item order
+  // (the order the sweeps visit them); cr is the next chunk's register
+  uint32_t rw[RC > 0 ? 3 * RC : 3] = {};
+  ResState rs{0u, 0u, 0u, 0u};
+  if constexpr (RC > 0) {
+    for (int32_t ph = 0; ph < a.n_phases; ++ph) {
+      const uint32_t b = ro(a.wave_ptr, (size_t)ph * stride + gw), e = ro(a.wave_ptr, (size_t)ph * stride + gw + 1);
+      for (uint32_t i = b; i < e; ++i) load_resident<RC>(a, ro_item(a.items, i), lane, rw, rs);
+    }
+  }
   // sweep t draws Philox blocks when t is divisible by 4 or starts the call;
   // otherwise its flip bits sit in plane (t mod 4) - 1
   auto plane_of = [&](int64_t t) -> int { return (t == a.t_begin || (t & 3) == 0) ? -1 : (int)(t & 3) - 1; };
   uint32_t epoch = 0;
   uint32_t run_w = 0;  // first spin word written since the last grid barrier
-  const size_t stride = (size_t)a.nw + 1;
   uint32_t ib = ro(a.wave_ptr, gw), ie = ro(a.wave_ptr, gw + 1);
   Fetched<L, ENC> fa, fb, fc;
   Item ita;
   if (ib < ie) {
     ita = ro_item(a.items, ib);
-    fetch<L, ENC, FIELD>(a, ita, lane, fa, plane_of(a.t_begin));
+    fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, plane_of(a.t_begin));
   }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
     const int plane = plane_of(t);
+    rs.cr = 0;
+    rs.j = 0;
     for (int32_t ph = 0; ph < a.n_phases; ++ph) {
       // Items of this phase.  On entry fa holds the loads of item ib.  The
       // loop is unrolled by the pipeline depth so the buffers change roles
@@ -556,30 +671,30 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         Item itb, itc, pre;
         if (ib + 1 < ie) {
           itb = ro_item(a.items, ib + 1);
-          fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
+          fetch<L, ENC, FIELD, RC>(a, itb, lane, fb, plane);
         }
         if (ib + 2 < ie) pre = ro_item(a.items, ib + 2);
         for (uint32_t i = ib; i < ie; i += 3) {
           if (i + 2 < ie) {
             itc = pre;
-            fetch<L, ENC, FIELD>(a, itc, lane, fc, plane);
+            fetch<L, ENC, FIELD, RC>(a, itc, lane, fc, plane);
             if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
-          compute<L, ENC, USE_LDS, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
           if (i + 1 >= ie) break;
           if (i + 3 < ie) {
             ita = pre;
-            fetch<L, ENC, FIELD>(a, ita, lane, fa, plane);
+            fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, plane);
             if (i + 4 < ie) pre = ro_item(a.items, i + 4);
           }
-          compute<L, ENC, USE_LDS, FIELD>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
           if (i + 2 >= ie) break;
           if (i + 4 < ie) {
             itb = pre;
-            fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
+            fetch<L, ENC, FIELD, RC>(a, itb, lane, fb, plane);
             if (i + 5 < ie) pre = ro_item(a.items, i + 5);
           }
-          compute<L, ENC, USE_LDS, FIELD>(a, itc, lane, fc, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, itc, lane, fc, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
         }
       } else if (kUnrolled) {
         // one item ahead: fa, fb in rotation
@@ -588,17 +703,17 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         for (uint32_t i = ib; i < ie; i += 2) {
           if (i + 1 < ie) {
             itb = pre;
-            fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
+            fetch<L, ENC, FIELD, RC>(a, itb, lane, fb, plane);
             if (i + 2 < ie) pre = ro_item(a.items, i + 2);
           }
-          compute<L, ENC, USE_LDS, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
           if (i + 1 >= ie) break;
           if (i + 2 < ie) {
             ita = pre;
-            fetch<L, ENC, FIELD>(a, ita, lane, fa, plane);
+            fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, plane);
             if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
-          compute<L, ENC, USE_LDS, FIELD>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
         }
       } else {
         // one item ahead, rolled: the copy waits for the next item's loads
@@ -607,9 +722,9 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           Item itb;
           if (more) {
             itb = ro_item(a.items, i + 1);
-            fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
+            fetch<L, ENC, FIELD, RC>(a, itb, lane, fb, plane);
           }
-          compute<L, ENC, USE_LDS, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
           if (more) {
             ita = itb;
             fa = fb;
@@ -638,14 +753,14 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           }
           if (ib < ie) {
             ita = ro_item(a.items, ib);
-            fetch<L, ENC, FIELD>(a, ita, lane, fa, next_plane);
+            fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, next_plane);
           }
           continue;
         }
         bar_arrive(a, fenced, epoch + 1u);
         if (ib < ie) {
           ita = ro_item(a.items, ib);
-          fetch<L, ENC, FIELD>(a, ita, lane, fa, next_plane);
+          fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, next_plane);
         }
         ++epoch;
         if (!bar_wait(a, epoch, fenced, s_ok)) return;
@@ -660,7 +775,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         // only this workgroup writes (its LDS copy of those is the freshest).
         if (ib < ie) {
           ita = ro_item(a.items, ib);
-          fetch<L, ENC, FIELD>(a, ita, lane, fa, next_plane);
+          fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, next_plane);
         }
         if (USE_LDS && (uint64_t)t % a.async_refresh == 0u) {
           const size_t oi = ((size_t)ph * gridDim.x + blockIdx.x) * 2;
@@ -686,7 +801,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         // one workgroup: its LDS copy is current
         if (ib < ie) {
           ita = ro_item(a.items, ib);
-          fetch<L, ENC, FIELD>(a, ita, lane, fa, next_plane);
+          fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, next_plane);
         }
         if (!a.async_mode || last_phase) {
           if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -948,9 +1063,9 @@ hipError_t set_lds_limit(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int L, int ENC, bool USE_LDS, bool FIELD>
+template <int L, int ENC, bool USE_LDS, bool FIELD, int RC = 0>
 hipError_t launch_anneal_t(const AnnealArgs &a, int grid, size_t lds_bytes, hipStream_t s) {
-  auto kern = k_anneal<L, ENC, USE_LDS, FIELD>;
+  auto kern = k_anneal<L, ENC, USE_LDS, FIELD, RC>;
   if (lds_bytes > kLdsBudget) return hipErrorInvalidValue;
   AnnealArgs copy = a;
   void *args[] = {&copy};
@@ -989,6 +1104,16 @@ hipError_t occupancy_t(int *blocks, size_t lds_bytes) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &b1, reinterpret_cast<const void *>(k_anneal<L, ENC, USE_LDS, true>), kAnnealBlock, 0);
   *blocks = b0 < b1 ? b0 : b1;
+  if constexpr (kHasResident<L, ENC, USE_LDS>) {
+    // and the register-resident variants
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &b0, reinterpret_cast<const void *>(k_anneal<L, ENC, USE_LDS, false, kResChunks>), kAnnealBlock, 0);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &b1, reinterpret_cast<const void *>(k_anneal<L, ENC, USE_LDS, true, kResChunks>), kAnnealBlock, 0);
+    *blocks = std::min(*blocks, std::min(b0, b1));
+  }
   return e;
 }
 
@@ -1007,7 +1132,15 @@ hipError_t occupancy_t(int *blocks, size_t lds_bytes) {
 
 namespace {
 template <int L, int ENC>
-hipError_t anneal_LE(const AnnealArgs &a, bool use_lds, int grid, size_t lds, hipStream_t s) {
+hipError_t anneal_LE(const AnnealArgs &a, bool use_lds, bool resident, int grid, size_t lds, hipStream_t s) {
+  if (resident) {
+    if constexpr (kHasResident<L, ENC, true>) {
+      if (!use_lds) return hipErrorInvalidValue;
+      return a.bias != nullptr ? launch_anneal_t<L, ENC, true, true, kResChunks>(a, grid, lds, s)
+                               : launch_anneal_t<L, ENC, true, false, kResChunks>(a, grid, lds, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (a.bias != nullptr)
     return use_lds ? launch_anneal_t<L, ENC, true, true>(a, grid, lds, s)
                    : launch_anneal_t<L, ENC, false, true>(a, grid, lds, s);
@@ -1015,10 +1148,10 @@ hipError_t anneal_LE(const AnnealArgs &a, bool use_lds, int grid, size_t lds, hi
                  : launch_anneal_t<L, ENC, false, false>(a, grid, lds, s);
 }
 template <int L>
-hipError_t anneal_L(const AnnealArgs &a, int enc, bool use_lds, int grid, size_t lds, hipStream_t s) {
-  if (enc == kEncPm1) return anneal_LE<L, kEncPm1>(a, use_lds, grid, lds, s);
-  if (enc == kEncW8) return anneal_LE<L, kEncW8>(a, use_lds, grid, lds, s);
-  return anneal_LE<L, kEncWide>(a, use_lds, grid, lds, s);
+hipError_t anneal_L(const AnnealArgs &a, int enc, bool use_lds, bool resident, int grid, size_t lds, hipStream_t s) {
+  if (enc == kEncPm1) return anneal_LE<L, kEncPm1>(a, use_lds, resident, grid, lds, s);
+  if (enc == kEncW8) return anneal_LE<L, kEncW8>(a, use_lds, resident, grid, lds, s);
+  return anneal_LE<L, kEncWide>(a, use_lds, resident, grid, lds, s);
 }
 template <int L, int ENC>
 hipError_t batch_LE(const AnnealArgs &a, int waves, int grid, size_t lds, hipStream_t s) {
@@ -1094,9 +1227,9 @@ hipError_t launch_best(const unsigned long long *sums, int32_t R, int32_t L, int
   return hipGetLastError();
 }
 
-hipError_t launch_anneal(int L, int enc, bool use_lds, const AnnealArgs &a, int grid, size_t lds_bytes,
-                         hipStream_t s) {
-  ISING_DISPATCH_L(L, anneal_L, a, enc, use_lds, grid, lds_bytes, s);
+hipError_t launch_anneal(int L, int enc, bool use_lds, bool resident, const AnnealArgs &a, int grid,
+                         size_t lds_bytes, hipStream_t s) {
+  ISING_DISPATCH_L(L, anneal_L, a, enc, use_lds, resident, grid, lds_bytes, s);
 }
 
 hipError_t launch_anneal_batch(int L, int enc, bool resident, int waves, const AnnealArgs &a, int grid,

@@ -309,12 +309,28 @@ std::vector<int32_t> phase_classes(const HostLayout &L, const std::vector<int64_
 }
 
 std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int32_t> &phase_cls, int32_t nw,
-                                      const std::vector<uint32_t> &local, int32_t local_waves) {
+                                      const std::vector<uint32_t> &local, int32_t local_waves, bool rotate_small) {
   const int32_t n_ph = (int32_t)phase_cls.size() - 1;
   std::vector<uint32_t> out((size_t)n_ph * (nw + 1));
+  uint64_t rot = 0;
   for (int32_t p = 0; p < n_ph; ++p) {
     const uint32_t b = L.phase_items[phase_cls[p]], e = L.phase_items[phase_cls[p + 1]];
     const int32_t nwp = local[p] ? std::min(local_waves, nw) : nw;  // waves that share the phase
+    uint32_t *o = &out[(size_t)p * (nw + 1)];
+    const uint32_t n = e - b;
+    if (rotate_small && !local[p] && n > 0 && n <= (uint32_t)nwp) {
+      // one item per wavefront, item j on wavefront k + j s: the start k
+      // moves from phase to phase so that no wavefront collects the first
+      // item of every small phase
+      const uint32_t s = (uint32_t)nwp / n, k = (uint32_t)(rot % s);
+      rot += n;
+      for (int32_t w = 0; w <= nw; ++w) {
+        const uint32_t before = w <= (int32_t)k ? 0u : std::min<uint32_t>(n, ((uint32_t)w - k + s - 1) / s);
+        o[w] = b + before;
+      }
+      o[nw] = e;
+      continue;
+    }
     std::vector<uint64_t> prefix(e - b + 1, 0);
     for (uint32_t i = b; i < e; ++i) {
       const Item &it = L.items[i];
@@ -323,7 +339,6 @@ std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int
       prefix[i - b + 1] = prefix[i - b] + cost;
     }
     const uint64_t total = prefix.back();
-    uint32_t *o = &out[(size_t)p * (nw + 1)];
     uint32_t j = 0;
     for (int32_t w = 0; w <= nw; ++w) {
       if (w >= nwp) {
@@ -338,6 +353,23 @@ std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int
     o[nw] = e;
   }
   return out;
+}
+
+uint64_t max_wave_chunks(const HostLayout &L, const std::vector<uint32_t> &wave_ptr, int32_t n_ph, int32_t nw,
+                         uint64_t *max_items) {
+  uint64_t most = 0, items = 0;
+  for (int32_t w = 0; w < nw; ++w) {
+    uint64_t sum = 0, cnt = 0;
+    for (int32_t p = 0; p < n_ph; ++p)
+      for (uint32_t i = wave_ptr[(size_t)p * (nw + 1) + w]; i < wave_ptr[(size_t)p * (nw + 1) + w + 1]; ++i) {
+        sum += (L.items[i].len4 + L.items[i].g - 1) / L.items[i].g;
+        ++cnt;
+      }
+    most = std::max(most, sum);
+    items = std::max(items, cnt);
+  }
+  if (max_items != nullptr) *max_items = items;
+  return most;
 }
 
 std::vector<uint32_t> own_words(const HostLayout &L, const std::vector<uint32_t> &wave_ptr, int32_t n_ph,

@@ -77,15 +77,23 @@ std::vector<int32_t> phase_classes(const HostLayout &L, const std::vector<int64_
 
 // Splits each phase's items over nw wavefronts in contiguous runs of about
 // equal cost; a phase with local[p] != 0 goes to the first local_waves
-// wavefronts (one workgroup) only.  Returns [n_phases][nw + 1] item offsets.
+// wavefronts (one workgroup) only.  rotate_small: a phase with no more items
+// than wavefronts gets one item per wavefront, spaced evenly, from a start
+// that moves from phase to phase.  Returns [n_phases][nw + 1] item offsets.
 std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int32_t> &phase_cls, int32_t nw,
-                                      const std::vector<uint32_t> &local, int32_t local_waves);
+                                      const std::vector<uint32_t> &local, int32_t local_waves, bool rotate_small);
 
 // For each phase and workgroup (waves_per_block consecutive wavefronts), the
 // 64-bit spin words written by that workgroup alone: [lo, hi), or [0, 0).
 // Words shared with a neighbouring workgroup's items are left out.
 std::vector<uint32_t> own_words(const HostLayout &L, const std::vector<uint32_t> &wave_ptr, int32_t n_ph,
                                 int32_t grid, int32_t waves_per_block, int Lbits);
+
+// Largest number of chunks per lane, sum of ceil(len4 / g) over its items,
+// that one wavefront's items of all phases hold; *max_items (if not NULL):
+// the most items one wavefront has in all phases.
+uint64_t max_wave_chunks(const HostLayout &L, const std::vector<uint32_t> &wave_ptr, int32_t n_ph, int32_t nw,
+                         uint64_t *max_items);
 
 // Verifies that every item addresses only memory inside the layout (index
 // ranges of entries, slots and spin words).  Returns false with a message.

@@ -159,9 +159,15 @@ def algorithmic_bytes_per_sweep(g, info):
     return g.nnz * per_edge + g.n * 4 + g.n * L / 8.0
 
 
-def moved_bytes_per_sweep(info):
-    """Bytes the kernel streams per sweep per group, padding and metadata included."""
-    return info["edge_bytes"] + info["vertex_bytes"] + info["spin_bytes"] + 16 * info["items"]
+def moved_bytes_per_launch(info, sweeps, resident):
+    """Bytes the kernel streams per launch per group, padding and metadata included.
+
+    With register-resident entries the edge stream is read once per launch
+    and the caller ids only in the sweeps that draw (one in four)."""
+    per_sweep = info["spin_bytes"] + 16 * info["items"]
+    if resident:
+        return info["edge_bytes"] + sweeps * (per_sweep + info["vertex_bytes"] / 4.0)
+    return sweeps * (per_sweep + info["edge_bytes"] + info["vertex_bytes"])
 
 
 def cpu_baseline(g, sweeps_total, replicas, seed, budget_s):
@@ -277,7 +283,8 @@ def main():
     value = g.n * R * M * args.steps / (total_ms / 1e3)
 
     alg = algorithmic_bytes_per_sweep(g, info) * info["n_groups"] * M
-    moved = moved_bytes_per_sweep(info) * info["n_groups"] * M
+    resident = info["bins"] == 0 and bool(info["resident_edges"] & (2 if mode == 1 else 1))
+    moved = moved_bytes_per_launch(info, M, resident) * info["n_groups"]
     mean_anneal_s = float(np.mean(anneal_ms)) / 1e3
     achieved = alg / mean_anneal_s / 1e9
     traffic = measured_traffic(args.traffic, args.workload, args.mode) if M == wl["sweeps"] else None
@@ -304,7 +311,8 @@ def main():
                      "kernel": "k_anneal_batch" if info["bins"] > 0 else "k_anneal",
                      "anneal_ms_mean": float(np.mean(anneal_ms)),
                      "anneal_ms_min": float(np.min(anneal_ms)),
-                     "algorithmic_bytes_per_launch": alg, "moved_bytes_per_launch": moved},
+                     "algorithmic_bytes_per_launch": alg, "moved_bytes_per_launch": moved,
+                     "resident_edges": resident},
         "final_cut_last_step": int(cuts[0]),
         "sources_sha256": sources_digest(),
         "create_s": create_s,

@@ -356,8 +356,12 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
   const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs, K = 64u >> gs;
   const uint32_t r = (uint32_t)lane >> gs, gl = (uint32_t)lane & (G - 1u);
   const uint32_t slot = it.id + r;
-  f.vid = plane < 0 ? a.vid[slot] : 0;  // the caller id only keys the Philox draws
-  f.bias = FIELD ? a.bias[slot] : 0;
+  // the caller id only keys the Philox draws.  With resident state
+  // (RC > 0) compute loads these itself: a prefetched register would make
+  // every item wait for all earlier stores (one counter covers loads and
+  // stores), also in sweeps that load nothing.
+  f.vid = RC == 0 && plane < 0 ? a.vid[slot] : 0;
+  f.bias = FIELD && RC == 0 ? a.bias[slot] : 0;
   // Only this item (so this workgroup) writes its row's spin and flip bits,
   // and only those bits are used: workgroup-scope loads are enough.
   f.ownw = RC > 0 ? 0u : ld_workgroup(a.spins + ((slot * L) >> 5));
@@ -392,11 +396,16 @@ struct ResState {
   uint32_t cr, j, own, flip;
 };
 
+// LDS word of the anneal's mirror array past the spin state that holds 0:
+// a resident chunk past a lane's share of its row points all four entries
+// (sign 0) at it, so it adds nothing to the count and needs no test.
+constexpr uint32_t kZeroWord = (uint32_t)(kLdsBudget / 4) + 1u;
+static_assert(kZeroWord * 32u < (1u << 23), "the zero word must be addressable by a 24-bit entry");
+
 // Register-resident chunks of one item (+-1 entries): this lane's chunks
 // g, g + G, ... go to registers rw[3 cr ...] onwards, packed by pack24; cr
 // advances by the item's chunks per lane, ceil(len4 / G), which is the same
-// for every lane.  Registers of chunks past a lane's share are left as they
-// are (compute skips them by the same test).  Also loads the row's spin.
+// for every lane.  Also loads the row's spin.
 template <int RC>
 __device__ __forceinline__ void load_resident(const AnnealArgs &a, const Item &it_in, int lane, uint32_t (&rw)[3 * RC],
                                               ResState &rs) {
@@ -409,8 +418,9 @@ __device__ __forceinline__ void load_resident(const AnnealArgs &a, const Item &i
   for (int c = 0; c < RC; ++c) {
     const uint32_t k = (uint32_t)c - rs.cr;
     const uint32_t q = gl + k * G;
-    if (k < nch && q < it.len4) {
-      const uint4 x = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + ((q << ks) + r) * 16u);
+    if (k < nch) {
+      uint4 x = make_uint4(kZeroWord * 32u, kZeroWord * 32u, kZeroWord * 32u, kZeroWord * 32u);
+      if (q < it.len4) x = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + ((q << ks) + r) * 16u);
       pack24(x, &rw[3 * c]);
     }
   }
@@ -448,7 +458,7 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
 #pragma unroll
     for (int c = 0; c < RC; ++c) {
       const uint32_t k = (uint32_t)c - cb;
-      if (k < nch && gl + k * G < it.len4) {
+      if (k < nch) {
         // opaque copies: without them the compiler hoists every entry's
         // decoded address out of the sweep loop, three registers per entry
         uint32_t x[3] = {rw[3 * c], rw[3 * c + 1], rw[3 * c + 2]};
@@ -510,8 +520,9 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   // form above; without a field that never changed a decision (the field
   // is odd, hence nonzero), with one it could, so it is taken out here.
   if (FIELD) {
-    const int32_t hb = f.bias >> 1;
-    const uint32_t odd = kPm1 ? (uint32_t)f.bias & 1u : 0u;
+    const int32_t bias = RC > 0 ? a.bias[slot] : f.bias;
+    const int32_t hb = bias >> 1;
+    const uint32_t odd = kPm1 ? (uint32_t)bias & 1u : 0u;
     const uint32_t own_bits = RC > 0 ? (rs->own >> rs->j) & 1u : (f.ownw >> ((slot * L) & 31u)) & lmask<L>();
 #pragma unroll
     for (int j = 0; j < L; ++j) h[j] += hb - (odd ? (int32_t)(((own_bits >> j) & 1u) << 1) - 1 : 0);
@@ -522,7 +533,7 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   uint32_t later[3];
   uint32_t flips;
   if (draws)
-    flips = draw_flips<L>(f.vid, t, a, later);
+    flips = draw_flips<L>(RC > 0 ? a.vid[slot] : f.vid, t, a, later);
   else if (RC > 0)
     flips = (rs->flip >> (3u * rs->j + (t & 3u) - 1u)) & 1u;  // sweep t's plane is (t mod 4) - 1
   else
@@ -629,6 +640,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   constexpr bool kDeep = ENC == kEncPm1 && L <= 4 && RC == 0;
   constexpr bool kUnrolled = L <= 4 && RC == 0;
   if (USE_LDS) {
+    if (RC > 0 && threadIdx.x == 0) mirror[kZeroWord] = 0u;
     restage(a, lds, 0, a.n_words / 2, threadIdx.x, blockDim.x);
     __syncthreads();
   }

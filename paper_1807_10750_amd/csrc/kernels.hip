@@ -550,7 +550,10 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
     // the item owns whole words: plain coherent stores
     if (L == 1 && G == 1u) {
       const unsigned long long b = __ballot(nm & 1u);
-      if (lane == 0) {
+      // with resident state the word's current value is known: an
+      // unchanged word is not stored again (nothing else writes it)
+      const bool store = RC == 0 || __ballot(nm != own) != 0ull;
+      if (lane == 0 && store) {
         st_coherent64(reinterpret_cast<unsigned long long *>(a.spins) + (it.id >> 6), b);
         if (USE_LDS) reinterpret_cast<unsigned long long *>(lds)[(it.id >> 6) - (woff >> 1)] = b;
       }

@@ -68,3 +68,34 @@ def test_null_handle_arguments_are_rejected_without_a_device():
     assert lib.isingCreate(ctypes.byref(h), -1, 0, None, None, None, 0, 1, None) == 1
     lib.isingCut.argtypes = [ctypes.c_void_p] * 4
     assert lib.isingCut(None, None, None, None) == 1
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    # gcc compiles the header and prints size and field offsets of the two
+    # structs the binding mirrors; ctypes must agree field by field
+    import shutil
+    import subprocess
+    from paper_1807_10750_amd import ising
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        import pytest
+        pytest.skip("no host C compiler")
+    checks = {"ising_info_t": ising.Info, "ising_schedule_t": ising.Schedule}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "ising.h"', "int main(void) {"]
+    for cname, py in checks.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        cname, key, val = line.split()
+        got[(cname, key)] = int(val)
+    for cname, py in checks.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)

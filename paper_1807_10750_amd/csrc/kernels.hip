@@ -394,7 +394,15 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
 // register, j the next item's index.
 struct ResState {
   uint32_t cr, j, own, flip;
+  uint32_t pw, px;  // spin word with a pending XOR and the XOR (wave-uniform)
 };
+
+// Applies a wavefront's pending XOR to the global spin state.
+__device__ __forceinline__ void flush_pending(const AnnealArgs &a, ResState &rs, int lane) {
+  if (rs.px != 0u && lane == 0)
+    __hip_atomic_fetch_xor(a.spins + rs.pw, rs.px, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  rs.px = 0u;
+}
 
 // LDS word of the anneal's mirror array past the spin state that holds 0:
 // a resident chunk past a lane's share of its row points all four entries
@@ -590,7 +598,17 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
     // all K rows share one word with other items: exact XOR of the changes
     uint32_t chg = rep ? (own ^ nm) << sh : 0u;
     for (uint32_t off = G; off < 64u; off <<= 1) chg |= __shfl_xor(chg, (int)off);
-    if (lane == 0 && chg != 0u) {
+    if constexpr (RC > 0) {
+      // consecutive items of a wavefront often share the word: their
+      // changes are combined into one global XOR (the LDS copy at once)
+      const uint32_t wd = uni(bit0 >> 5), cu = uni(chg);
+      if (lane == 0 && cu != 0u) atomicXor(lds + wd, cu);
+      if (wd != rs->pw) {
+        flush_pending(a, *rs, lane);
+        rs->pw = wd;
+      }
+      rs->px ^= cu;
+    } else if (lane == 0 && chg != 0u) {
       __hip_atomic_fetch_xor(a.spins + (bit0 >> 5), chg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (USE_LDS) atomicXor(lds + ((bit0 >> 5) - woff), chg);
     }
@@ -652,7 +670,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   // resident chunks of this wavefront's items, phase by phase in item order
   // (the order the sweeps visit them); cr is the next chunk's register
   uint32_t rw[RC > 0 ? 3 * RC : 3] = {};
-  ResState rs{0u, 0u, 0u, 0u};
+  ResState rs{0u, 0u, 0u, 0u, 0u, 0u};
   if constexpr (RC > 0) {
     for (int32_t ph = 0; ph < a.n_phases; ++ph) {
       const uint32_t b = ro(a.wave_ptr, (size_t)ph * stride + gw), e = ro(a.wave_ptr, (size_t)ph * stride + gw + 1);
@@ -746,6 +764,8 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           }
         }
       }
+      // a phase's updates are published before it ends
+      if constexpr (RC > 0) flush_pending(a, rs, lane);
       // the next phase's item range and first item
       const bool last_phase = ph + 1 == a.n_phases;
       const int32_t nph = last_phase ? 0 : ph + 1;
@@ -792,7 +812,13 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           ita = ro_item(a.items, ib);
           fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, next_plane);
         }
-        if (USE_LDS && (uint64_t)t % a.async_refresh == 0u) {
+        // At the end of a sweep the workgroup arrives first (its stores of
+        // the sweep are complete) and refreshes after: the refresh then
+        // overlaps the other workgroups' work instead of delaying them.
+        // The last sweep of the call needs no refresh.
+        const bool sweep_end = last_phase && !done;
+        if (sweep_end) bar_arrive(a, fenced, epoch + 1u);
+        if (USE_LDS && !done && (uint64_t)t % a.async_refresh == 0u) {
           const size_t oi = ((size_t)ph * gridDim.x + blockIdx.x) * 2;
           const uint32_t o0 = ro(a.own_w64, oi), o1 = ro(a.own_w64, oi + 1);
           const uint32_t b = ro(a.cls_w64, ph), e = ro(a.cls_w64, ph + 1);
@@ -805,10 +831,9 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
             restage(a, lds, b, e, first, blockDim.x);
           }
         }
-        if (last_phase && !done) {
+        if (sweep_end) {
           // sweeps stay within async_slack of each other: after its sweep
           // k, a workgroup waits for every workgroup's sweep k - slack
-          bar_arrive(a, fenced, epoch + 1u);
           ++epoch;
           if (epoch > a.async_slack && !bar_wait(a, epoch - a.async_slack, fenced, s_ok)) return;
         }

@@ -868,7 +868,7 @@ ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *s, uint64_t 
   a.seed_lo = (uint32_t)seed;
   a.seed_hi = (uint32_t)(seed >> 32);
   a.spin_limit = (uint32_t)std::max<int64_t>(1000, env_int("ISING_BARRIER_POLLS", 20000000));
-  a.async_slack = (uint32_t)std::min<int64_t>(8, std::max<int64_t>(0, env_int("ISING_ASYNC_SLACK", 1)));
+  a.async_slack = (uint32_t)std::min<int64_t>(8, std::max<int64_t>(0, env_int("ISING_ASYNC_SLACK", 2)));
   a.bar_flags = env_int("ISING_BARRIER_FLAGS", 0) != 0 && g->grid <= kBarMaxGrid ? 1u : 0u;
   a.async_refresh = (uint32_t)std::min<int64_t>(64, std::max<int64_t>(1, env_int("ISING_ASYNC_REFRESH", 1)));
   if (g->batch) {

@@ -20,8 +20,11 @@
 // Spin state is an L-bit mask per slot (replica bits) packed in uint32
 // words.  When it fits, each workgroup keeps a copy of the whole state in
 // LDS and neighbour gathers are LDS reads; the edge stream is read once per
-// sweep with 16-byte coalesced loads.  All global spin traffic uses
-// agent-scope atomics, which are coherent across the XCDs' L2 caches.
+// sweep with 16-byte coalesced loads, or, with +-1 weights and one replica
+// bit per slot, once per call into registers that every wavefront keeps for
+// all its sweeps (its items never change within a call).  All global spin
+// traffic uses agent-scope atomics, which are coherent across the XCDs' L2
+// caches.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"

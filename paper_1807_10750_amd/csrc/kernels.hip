@@ -173,23 +173,24 @@ __device__ __forceinline__ void pack24(const uint4 &x, uint32_t *w) {
   w[1] = (p1 >> 8) | (p2 << 16);
   w[2] = (p2 >> 16) | (p3 << 8);
 }
-// One 24-bit entry in the low bits of x (bits above 23 are ignored).
-template <int L, typename P>
-__device__ __forceinline__ void accumulate24(int32_t (&c)[L], uint32_t x, P words) {
-  const uint32_t slot = x & 0x7FFFFFu;
-  const uint32_t word = words[(slot * L) >> 5];
-  const uint32_t m = L == 1 ? word : word >> ((slot * L) & 31u);
-  const uint32_t off0 = L == 1 ? x : 0u;  // bits [4:0] of x are slot bits [4:0]
-  const uint32_t neg = (x >> 23) & 1u;
-#pragma unroll
-  for (int j = 0; j < L; ++j) c[j] += (int32_t)(__builtin_amdgcn_ubfe(m, off0 + (uint32_t)j, 1u) ^ neg);
-}
+// The chunk's four gathers are issued together and waited for once (left
+// to itself the scheduler waited after each).
 template <int L, typename P>
 __device__ __forceinline__ void accumulate_packed(int32_t (&c)[L], const uint32_t *w, P words) {
-  accumulate24<L>(c, w[0], words);
-  accumulate24<L>(c, __builtin_amdgcn_alignbit(w[1], w[0], 24), words);
-  accumulate24<L>(c, __builtin_amdgcn_alignbit(w[2], w[1], 16), words);
-  accumulate24<L>(c, w[2] >> 8, words);
+  static_assert(L == 1, "resident chunks serve one replica bit per slot");
+  const uint32_t e0 = w[0], e1 = __builtin_amdgcn_alignbit(w[1], w[0], 24),
+                 e2 = __builtin_amdgcn_alignbit(w[2], w[1], 16), e3 = w[2] >> 8;
+  const uint32_t v0 = words[(e0 & 0x7FFFFFu) >> 5], v1 = words[(e1 & 0x7FFFFFu) >> 5],
+                 v2 = words[(e2 & 0x7FFFFFu) >> 5], v3 = words[(e3 & 0x7FFFFFu) >> 5];
+  // scheduling groups: the address arithmetic, the four LDS reads, the rest
+  __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+  __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+  __builtin_amdgcn_sched_group_barrier(0x002, 16, 0);
+  // bits [4:0] of an entry are its slot's bit within the word
+  c[0] += (int32_t)((__builtin_amdgcn_ubfe(v0, e0, 1u) ^ ((e0 >> 23) & 1u)) +
+                    (__builtin_amdgcn_ubfe(v1, e1, 1u) ^ ((e1 >> 23) & 1u)) +
+                    (__builtin_amdgcn_ubfe(v2, e2, 1u) ^ ((e2 >> 23) & 1u)) +
+                    (__builtin_amdgcn_ubfe(v3, e3, 1u) ^ ((e3 >> 23) & 1u)));
 }
 
 // Local update (Eq. 2 with J = -w, a zero field keeps the spin) of every

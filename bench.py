@@ -8,8 +8,12 @@ create-time host work, reported separately).
 
 Default workload: the 1,000,000-vertex power-law graph (exponent 2.5, mean
 degree 8, max degree 2000, weights +-1), 2000 sweeps of the linear flip
-schedule 0.1 -> 0, async mode -- the configuration whose edge stream is set
-against the HBM roofline.
+schedule 0.1 -> 0, async mode (every sweep synchronised, every neighbour value
+from the current or the previous sweep), largest-first colouring -- the
+configuration whose edge stream is set against the HBM roofline.  The line
+also carries, outside `value`: the run-ahead async option and deterministic
+mode on the same handle, an on-chip figure, and the CPU oracle on one core and
+on every host core.
 
 Prints one JSON line (see the repository's design notes for every field).
 """
@@ -146,14 +150,22 @@ def measured_traffic(path, workload, mode):
 
 
 def algorithmic_bytes_per_sweep(g, info):
-    """Bytes one sweep of one replica group must move in this layout.
+    """Bytes the method must stream per sweep and replica group, layout-free.
 
-    Per directed edge: the 4-byte entry (neighbour slot with the weight's sign
-    or the int8 weight packed in), plus 1 byte of weight for graphs too large
-    to pack it.  Per vertex:
-    its 4-byte caller id (the flip counter) and the write of its new spin
-    mask (L bits).  Padding and work-item metadata are overhead, not counted.
+    Per directed edge a 4-byte neighbour id and a 1-byte weight; per vertex a
+    4-byte row pointer, and a 1-byte read and a 1-byte write of each of the
+    group's L spins (int8 spins).  For the 1M-vertex power-law graph (L = 1)
+    that is 8e6 * 5 + 1e6 * 6 = 46 MB per sweep.
     """
+    L = info["replicas_per_group"]
+    return g.nnz * 5 + g.n * (4 + 2 * L)
+
+
+def layout_bytes_per_sweep(g, info):
+    """The same streams in this library's layout: one 4-byte entry per
+    directed edge (neighbour slot with the weight's sign or int8 weight packed
+    in; +1 byte of weight when it cannot be packed), the 4-byte caller id and
+    the L-bit spin mask written per vertex."""
     per_edge = 5 if info["encoding"] == 2 else 4
     L = info["replicas_per_group"]
     return g.nnz * per_edge + g.n * 4 + g.n * L / 8.0
@@ -170,24 +182,49 @@ def moved_bytes_per_launch(info, sweeps, resident):
     return sweeps * (per_sweep + info["edge_bytes"] + info["vertex_bytes"])
 
 
-def cpu_baseline(g, sweeps_total, replicas, seed, budget_s):
-    """Time the CPU oracle (single-threaded C) on a bounded prefix of the schedule."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, sweeps_total, seed, budget_s, coloring_lf):
+    """Time the CPU oracle on a bounded prefix of the same schedule.
+
+    Two legs of budget_s / 2 each: the sequential oracle (one core, the
+    reference implementation as it stands) and its colour-parallel form on
+    every host core (OpenMP over the vertices of one colour class, bit-identical
+    to the sequential one).  The reported value is the all-cores leg."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as O
-    col, nc = O.color(g)
+    col, nc = O.color(g, coloring_lf)
     order = O.order(col, nc)
     T = O.thresholds(0.1, 0.0, sweeps_total)
     s0 = O.init_spins(g.n, 1, seed)
-    t0 = time.perf_counter()
-    O.anneal(g, order, s0, T, seed, 0, 1)
-    one = max(time.perf_counter() - t0, 1e-6)
-    sweeps = int(max(1, min(sweeps_total, budget_s / one)))
-    t0 = time.perf_counter()
-    O.anneal(g, order, s0, T, seed, 0, sweeps)
-    dt = time.perf_counter() - t0
-    return {"value": g.n * sweeps / dt, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sweeps} of {sweeps_total} sweeps, 1 replica, same graph, sequential "
-                      f"(colour, id) order, {dt:.1f} s"}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn(0, 1)
+        one = max(time.perf_counter() - t0, 1e-6)
+        sweeps = int(max(1, min(sweeps_total, 0.5 * budget_s / one)))
+        t0 = time.perf_counter()
+        fn(0, sweeps)
+        return sweeps, time.perf_counter() - t0
+
+    seq_sweeps, seq_dt = timed(lambda a, b: O.anneal(g, order, s0, T, seed, a, b))
+    par_sweeps, par_dt = timed(lambda a, b: O.anneal_colour_parallel(g, col, nc, s0, T, seed, a, b))
+    threads = O.threads()
+    return {"value": g.n * par_sweeps / par_dt, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"colour-parallel oracle on {threads} threads: {par_sweeps} of {sweeps_total} sweeps "
+                      f"({par_dt:.1f} s); sequential oracle on 1 core: {seq_sweeps} sweeps ({seq_dt:.1f} s); "
+                      f"1 replica, same graph and schedule",
+            "single_core_value": g.n * seq_sweeps / seq_dt,
+            "nproc": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0)),
+            "cpu_model": cpu_model()}
 
 
 def main():
@@ -197,9 +234,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="powerlaw1m", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="async", choices=["async", "det"])
-    ap.add_argument("--coloring", default="ff", choices=["ff", "lf"])
+    ap.add_argument("--coloring", default="lf", choices=["ff", "lf"])
     ap.add_argument("--sweeps", type=int, default=None, help="override the schedule length")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle time (0 = skip)")
+    ap.add_argument("--no-extra", dest="extra", action="store_false",
+                    help="skip the run-ahead and deterministic context legs")
     ap.add_argument("--p-start", type=float, default=0.1, help="initial flip probability of the linear schedule")
     ap.add_argument("--time-to-cut", action="store_true",
                     help="also measure time-to-cut over a ladder of shorter schedules (untimed for 'value')")
@@ -262,32 +301,41 @@ def main():
     torch.cuda.synchronize()
     print("# warmup done", file=sys.stderr, flush=True)
 
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for i in range(args.steps):
-        gr.randomize(2000 + i)
-        ev[i][0].record(stream)
-        gr.anneal(sch, 2000 + i, mode)
-        ev[i][1].record(stream)
-        gr.cut_device(cut, energy)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_end)
-    anneal_ms = [a.elapsed_time(b) for a, b in ev]
+    def timed_anneals(n_steps, sch_, mode_, seed0):
+        """(total ms, per-anneal ms) of n_steps randomize + anneal + cut steps."""
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(n_steps)]
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_start.record(stream)
+        for i in range(n_steps):
+            gr.randomize(seed0 + i)
+            ev[i][0].record(stream)
+            gr.anneal(sch_, seed0 + i, mode_)
+            ev[i][1].record(stream)
+            gr.cut_device(cut, energy)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        return t_start.elapsed_time(t_end), [x.elapsed_time(y) for x, y in ev]
+
+    total_ms, anneal_ms = timed_anneals(args.steps, sch, mode, 2000)
     cuts = cut.cpu().numpy()
     ms_step = total_ms / args.steps
     value = g.n * R * M * args.steps / (total_ms / 1e3)
 
-    alg = algorithmic_bytes_per_sweep(g, info) * info["n_groups"] * M
+    groups = info["n_groups"]
+    alg = algorithmic_bytes_per_sweep(g, info) * groups * M
+    lay_b = layout_bytes_per_sweep(g, info) * groups * M
     resident = info["bins"] == 0 and bool(info["resident_edges"] & (2 if mode == 1 else 1))
-    moved = moved_bytes_per_launch(info, M, resident) * info["n_groups"]
+    moved = moved_bytes_per_launch(info, M, resident) * groups
     mean_anneal_s = float(np.mean(anneal_ms)) / 1e3
     achieved = alg / mean_anneal_s / 1e9
     traffic = measured_traffic(args.traffic, args.workload, args.mode) if M == wl["sweeps"] else None
+    # on-chip: in lock step every workgroup refreshes its LDS copy of each
+    # phase's spin words after the phase, i.e. the whole state once per sweep
+    lds_refresh = info["grid"] * info["spin_bytes"] * groups if info["bins"] == 0 else 0
+    us_sweep = mean_anneal_s / M * 1e6
     out = {
         "metric": "spin-updates/sec",
         "value": value,
@@ -303,26 +351,56 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "name": args.workload, "n": g.n, "nnz": g.nnz,
                    "sweeps": M, "replicas": R, "mode": args.mode, "coloring": args.coloring,
-                   "p_start": args.p_start,
+                   "p_start": args.p_start, "async_phases_budget": "1% of edges inside a phase",
                    "colors": info["n_colors"], "grid": info["grid"], "block": info["block"],
                    "lds_spins": bool(info["uses_lds"]), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_source": (os.path.relpath(args.traffic, ROOT) if traffic is not None else None),
                      "kernel": "k_anneal_batch" if info["bins"] > 0 else "k_anneal",
                      "anneal_ms_mean": float(np.mean(anneal_ms)),
                      "anneal_ms_min": float(np.min(anneal_ms)),
-                     "algorithmic_bytes_per_launch": alg, "moved_bytes_per_launch": moved,
+                     "us_per_sweep": us_sweep,
+                     "algorithmic_bytes_per_launch": alg,
+                     "algorithmic_bytes_definition": "per sweep: 5 B per directed edge (4 B col + 1 B w) + "
+                                                     "(4 + 2 L) B per vertex (row_ptr, spin read and write)",
+                     "layout_bytes_per_launch": lay_b,
+                     "layout_frac": lay_b / mean_anneal_s / 1e9 / HBM_PEAK_GBS,
+                     "moved_bytes_per_launch": moved,
                      "resident_edges": resident},
+        "onchip": {"lds_refresh_bytes_per_sweep": lds_refresh,
+                   "lds_refresh_GBs": lds_refresh / (mean_anneal_s / M) / 1e9,
+                   "lds_gathers_per_sweep": g.nnz * groups,
+                   "lds_gathers_per_s": g.nnz * groups / (mean_anneal_s / M),
+                   "note": "gathers are 4-byte LDS reads of neighbour spin words; the refresh copies each "
+                           "phase's spin words from global memory into every workgroup's LDS copy"},
         "final_cut_last_step": int(cuts[0]),
+        "max_sweep_gap": gr.info()["max_sweep_gap"],
         "sources_sha256": sources_digest(),
         "create_s": create_s,
     }
+    if args.extra and args.workload == "powerlaw1m" and mode == I.MODE_ASYNC:
+        # the run-ahead option (not the paper's scheme: a workgroup may run
+        # two sweeps ahead of the slowest one) and deterministic mode, timed
+        # on the same handle for context
+        os.environ["ISING_ASYNC_SLACK"] = "2"
+        try:
+            tot, per = timed_anneals(2, sch, I.MODE_ASYNC, 3000)
+        finally:
+            os.environ.pop("ISING_ASYNC_SLACK", None)
+        out["runahead2_async"] = {"value": g.n * R * M * 2 / (tot / 1e3), "us_per_sweep": float(np.mean(per)) / M * 1e3,
+                                  "final_cut": int(cut.cpu().numpy()[0]), "max_sweep_gap": gr.info()["max_sweep_gap"]}
+        Md = 200
+        tot, per = timed_anneals(2, I.make_schedule(args.p_start, 0.0, Md), I.MODE_DETERMINISTIC, 4000)
+        out["deterministic"] = {"sweeps": Md, "us_per_sweep": float(np.mean(per)) / Md * 1e3,
+                                "value": g.n * R * Md * 2 / (tot / 1e3), "coloring": args.coloring}
     if args.time_to_cut:
         out["time_to_cut"] = time_to_cut(I, torch, gr, g, offsets, M, R, mode, [M // 16, M // 8, M // 4, M // 2])
     if args.cpu_budget > 0:
         print("# cpu baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(g, M, R, 1000, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(g, M, 1000, args.cpu_budget, args.coloring == "lf")
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+        out["gpu_over_cpu_single_core"] = value / out["cpu_baseline"]["single_core_value"]
     print(json.dumps(out), flush=True)
     gr.close()
 

@@ -91,11 +91,20 @@ typedef enum {
  *   greedy colouring (ising_coloring_t); the result equals a sequential
  *   sweep that visits vertices in (colour, id) order, bit for bit.  This
  *   generalises the checkerboard update the paper cites (Sec. IV-B).
- * ASYNC: the paper's race-tolerant update (Sec. IV-B): within a sweep no
- *   spin waits for another; a neighbour's value may be from this sweep or
- *   the previous one.  Work is still issued colour class by colour class,
- *   so most reads see this sweep's values.  Results vary from run to run;
- *   they are judged by cut statistics. */
+ * ASYNC: the paper's race-tolerant update (Sec. IV-B): every sweep is
+ *   synchronised, and inside a sweep a spin reads each neighbour's value
+ *   from this sweep or the previous one, never older.  Work is issued in
+ *   phases, runs of consecutive colour classes (a class holding at least
+ *   half of the vertices stays on its own), separated by device-wide
+ *   barriers: a neighbour in an earlier phase is read at this sweep's
+ *   value, one in a later phase at the previous sweep's, and one in the
+ *   same phase at either, as the update races with the neighbour's.
+ *   Results vary from run to run; they are judged by cut statistics.
+ *   The environment variable ISING_ASYNC_SLACK = s (1..8) instead lets a
+ *   workgroup run up to s sweeps ahead of the slowest one with no barrier
+ *   inside a sweep; neighbour values may then be older than the previous
+ *   sweep (isingGetInfo's max_sweep_gap shows how far apart workgroups
+ *   were). */
 typedef enum { ISING_MODE_DETERMINISTIC = 0, ISING_MODE_ASYNC = 1 } ising_mode_t;
 
 /* Greedy colouring rule.  FIRST_FIT visits vertices in increasing id;
@@ -212,8 +221,9 @@ typedef struct {
   int64_t items;            /* wavefront work items per sweep */
   int32_t bins;             /* batched mode: workgroups per replica group, each owning whole
                                connected components (0: one cooperative launch) */
-  int32_t resident_bins;    /* batched mode: bins whose +-1 edge entries are read from HBM once
-                               and kept in LDS (2 bytes each) for the whole anneal */
+  int32_t max_sweep_gap;    /* cooperative launch: the largest number of sweeps by which
+                               workgroups were apart at a grid barrier over the handle's life
+                               (0 or 1 in lock step); reading it synchronises the device */
   int32_t resident_edges;   /* cooperative launch: bit m set if mode m (0 deterministic, 1 async)
                                reads the +-1 edge entries from HBM once per call and keeps them
                                in registers (3 bytes each) for all its sweeps */

@@ -59,6 +59,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_ERR_ARG 1
@@ -342,6 +345,50 @@ int oracle_anneal(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
     }
   }
   return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same deterministic anneal with each colour class swept by all host   */
+/* threads at once (OpenMP).  No two vertices of a class are adjacent, so a */
+/* vertex's field reads only spins of other classes, all final for this     */
+/* phase: the result equals oracle_anneal in (colour, id) order bit for     */
+/* bit, whatever the thread count.  Used to time the oracle on every core.  */
+/* ------------------------------------------------------------------------ */
+int oracle_anneal_colour_parallel(int64_t n, const int64_t *row_ptr, const int32_t *col, const int8_t *w,
+                                  const int32_t *field, const int32_t *order, const int32_t *color,
+                                  int32_t n_colors, int32_t R, int8_t *spins, const uint32_t *T, uint64_t seed,
+                                  int64_t t_begin, int64_t t_end) {
+  if (t_begin < 0 || t_end < t_begin || n_colors < 0) return OR_ERR_ARG;
+  /* class c is order[first[c] .. first[c+1]) */
+  int64_t *first = (int64_t *)calloc((size_t)n_colors + 2, sizeof(int64_t));
+  if (!first) return OR_ERR_NOMEM;
+  for (int64_t v = 0; v < n; ++v) first[color[v] + 1] += 1;
+  for (int32_t c = 0; c < n_colors; ++c) first[c + 1] += first[c];
+  for (int32_t r = 0; r < R; ++r) {
+    int8_t *s = spins + (int64_t)r * n;
+    for (int64_t t = t_begin; t < t_end; ++t) {
+      for (int32_t c = 0; c < n_colors; ++c) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = first[c]; i < first[c + 1]; ++i) {
+          int64_t v = order[i];
+          int8_t x = field_update(v, row_ptr, col, w, field, s, s[v]);
+          if (flip_draw((uint32_t)v, (uint32_t)t, (uint32_t)r, seed) < T[t]) x = (int8_t)-x;
+          s[v] = x;
+        }
+      }
+    }
+  }
+  free(first);
+  return OR_OK;
+}
+
+/* Host threads the colour-parallel anneal uses. */
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 /* Jacobi bracket: all vertices of sweep t read the spins of sweep t-1. */

@@ -11,6 +11,7 @@
 #include <tuple>
 #include <vector>
 
+#include "internal.h"
 #include "ising.h"
 #include "kernels.h"
 #include "prep.h"
@@ -54,6 +55,9 @@ int64_t env_int(const char *name, int64_t dflt) {
   if (s == nullptr || *s == 0) return dflt;
   return std::strtoll(s, nullptr, 10);
 }
+
+// Edges allowed inside one async phase, in units of 0.1 % of all edges.
+constexpr int64_t kAsyncMergeBudget = 10;
 
 int pow2_at_least(int x) {
   int p = 1;
@@ -99,7 +103,6 @@ struct ising_graph_s {
   Item *d_items = nullptr;
   uint32_t *d_wave_ptr[2] = {nullptr, nullptr};  // per mode: [phases][nw + 1]
   uint32_t *d_own_w64[2] = {nullptr, nullptr};   // per mode: [phases][grid][2]
-  uint32_t *d_local[2] = {nullptr, nullptr};     // per mode: phase runs in workgroup 0 alone
   uint32_t *d_flips = nullptr;                   // 3 flip planes per replica group
   // batched mode: one workgroup per (bin of whole components, replica group)
   bool batch = false;
@@ -107,11 +110,7 @@ struct ising_graph_s {
   size_t batch_lds = 0;
   uint32_t *d_bin_wave_ptr = nullptr;            // [n_bins][colours][waves + 1]
   uint32_t *d_bin_words = nullptr;               // [n_bins + 1]
-  uint32_t *d_bin_chunks = nullptr;              // [n_bins][2] entry chunk range of each bin
-  uint32_t *d_bin_list = nullptr;                // resident bins, then the others
   bool res_edges[2] = {false, false};             // per mode: entries held in registers (kResChunks)
-  int32_t n_res_bins = 0;                        // bins whose entries sit in LDS
-  size_t res_lds = 0;                            // LDS of the resident launch
   uint32_t *d_cls_w64[2] = {nullptr, nullptr};   // per mode: phase -> spin word range
   int32_t n_phases[2] = {0, 0};
   uint32_t *d_spins = nullptr;
@@ -158,8 +157,7 @@ ising_status_t dev_alloc(T **p, size_t bytes, const char *what) {
 void free_all(ising_graph_s *g) {
   void *bufs[] = {g->d_entries, g->d_wts4, g->d_vid, g->d_items, g->d_wave_ptr[0], g->d_wave_ptr[1],
                   g->d_cls_w64[0], g->d_cls_w64[1], g->d_own_w64[0], g->d_own_w64[1], g->d_flips,
-                  g->d_local[0], g->d_local[1], g->d_bin_wave_ptr, g->d_bin_words, g->d_bin_chunks,
-                  g->d_bin_list,
+                  g->d_bin_wave_ptr, g->d_bin_words,
                   g->d_spins, g->d_thr, g->d_bar, g->d_cut, g->d_stage, g->d_bias,
                   g->d_best_cut, g->d_best_spins, g->d_best_mask, g->d_cutvals};
   for (void *b : bufs)
@@ -262,25 +260,10 @@ typedef std::tuple<int32_t, int64_t, int64_t, int32_t, int32_t, int32_t, size_t>
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune_cache;
 
-// The batched anneal: one launch for the bins that hold their entries in
-// LDS, one for the others (each with the LDS it needs).  a carries every
-// argument except the bin list window.
-hipError_t launch_batch_parts(const ising_graph_s *g, AnnealArgs a, int waves, hipStream_t st) {
-  a.bin_chunks = g->d_bin_chunks;
-  a.bin_list = g->d_bin_list;
-  const int32_t n_other = g->lay.n_bins - g->n_res_bins;
-  hipError_t e = hipSuccess;
-  if (g->n_res_bins > 0) {
-    a.list_off = 0;
-    a.n_bins = g->n_res_bins;
-    e = launch_anneal_batch(g->L, g->lay.enc, true, waves, a, g->n_res_bins * g->n_groups, g->res_lds, st);
-  }
-  if (e == hipSuccess && n_other > 0) {
-    a.list_off = (uint32_t)g->n_res_bins;
-    a.n_bins = n_other;
-    e = launch_anneal_batch(g->L, g->lay.enc, false, waves, a, n_other * g->n_groups, g->batch_lds, st);
-  }
-  return e;
+// The batched anneal: one workgroup per (bin, replica group).
+hipError_t launch_batch(const ising_graph_s *g, AnnealArgs a, int waves, hipStream_t st) {
+  a.n_bins = g->lay.n_bins;
+  return launch_anneal_batch(g->L, g->lay.enc, waves, a, g->lay.n_bins * g->n_groups, g->batch_lds, st);
 }
 
 // Times a short deterministic anneal of the handle with each candidate wave
@@ -328,7 +311,7 @@ ising_status_t time_batch_shapes(ising_graph_s *g, const std::vector<std::vector
     // the first launch warms caches and code; the second is timed
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
       if (rep == 1) e = hipEventRecord(e0, st);
-      if (e == hipSuccess) e = launch_batch_parts(g, a, waves[c], st);
+      if (e == hipSuccess) e = launch_batch(g, a, waves[c], st);
       if (rep == 1 && e == hipSuccess) e = hipEventRecord(e1, st);
     }
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -347,6 +330,97 @@ ising_status_t time_batch_shapes(ising_graph_s *g, const std::vector<std::vector
 }
 
 }  // namespace
+
+ising_status_t internal_fail(ising_status_t st, const std::string &msg) { return fail(st, msg); }
+
+void internal_clear_error() { g_last_error.clear(); }
+
+int internal_device(ising_graph_t g) { return g->device; }
+
+uint32_t internal_prob_threshold(double p) { return prob_threshold(p); }
+
+ising_status_t internal_check_anneal(ising_graph_t g, const ising_schedule_t *s, ising_mode_t mode,
+                                     int64_t sweep_begin, int64_t sweep_end) {
+  if (g == nullptr || s == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (mode != ISING_MODE_DETERMINISTIC && mode != ISING_MODE_ASYNC)
+    return fail(ISING_ERR_INVALID_ARGUMENT, "unknown mode");
+  if (s->n_sweeps < 1 || s->n_sweeps > ((int64_t)1 << 32))
+    return fail(ISING_ERR_INVALID_ARGUMENT, "n_sweeps must be in [1, 2^32]");
+  if (s->kind == ISING_SCHED_LINEAR) {
+    if (!(s->p_start >= 0.0 && s->p_start <= 1.0 && s->p_end >= 0.0 && s->p_end <= 1.0))
+      return fail(ISING_ERR_INVALID_ARGUMENT, "probabilities must lie in [0, 1]");
+  } else if (s->kind == ISING_SCHED_EXPLICIT) {
+    if (s->thresholds == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "thresholds is NULL");
+  } else {
+    return fail(ISING_ERR_INVALID_ARGUMENT, "unknown schedule kind");
+  }
+  if (sweep_begin < 0 || sweep_begin > sweep_end || sweep_end > s->n_sweeps)
+    return fail(ISING_ERR_INVALID_ARGUMENT, "need 0 <= sweep_begin <= sweep_end <= n_sweeps");
+  return ISING_OK;
+}
+
+// Launches sweeps [sweep_begin, sweep_end) with the threshold of sweep t at
+// thr[t - thr_base]; allocates nothing.
+ising_status_t internal_anneal(ising_graph_t g, uint64_t seed, ising_mode_t mode, int64_t sweep_begin,
+                               int64_t sweep_end, hipStream_t st, const uint32_t *thr, int64_t thr_base) {
+  AnnealArgs a{};
+  a.entries = reinterpret_cast<const uint4 *>(g->d_entries);
+  a.wts4 = g->d_wts4;
+  a.vid = g->d_vid;
+  a.bias = g->has_field ? g->d_bias : nullptr;
+  a.items = g->d_items;
+  const int m = mode == ISING_MODE_ASYNC ? 1 : 0;
+  a.wave_ptr = g->d_wave_ptr[m];
+  a.own_w64 = g->d_own_w64[m];
+  a.cls_w64 = g->d_cls_w64[m];
+  a.thr = thr;
+  a.thr_base = thr_base;
+  a.bar = g->d_bar;
+  a.n_words = g->n_words;
+  a.n_phases = g->n_phases[m];
+  a.nw = g->nw;
+  a.async_mode = mode == ISING_MODE_ASYNC ? 1 : 0;
+  a.seed_lo = (uint32_t)seed;
+  a.seed_hi = (uint32_t)(seed >> 32);
+  a.spin_limit = (uint32_t)std::max<int64_t>(1000, env_int("ISING_BARRIER_POLLS", 20000000));
+  // async run-ahead window (sweeps); 0, the default, keeps the workgroups in lock step
+  a.async_slack = (uint32_t)std::min<int64_t>(8, std::max<int64_t>(0, env_int("ISING_ASYNC_SLACK", 0)));
+  if (g->batch) {
+    a.spins = g->d_spins;
+    a.flips = g->d_flips;
+    a.wave_ptr = g->d_bin_wave_ptr;
+    a.bin_words = g->d_bin_words;
+    a.n_bins = g->lay.n_bins;
+    a.n_phases = g->n_colors;
+    a.r_total = (uint32_t)g->R;
+    a.t_begin = sweep_begin;
+    a.t_end = sweep_end;
+    HIP_TRY(launch_batch(g, a, g->batch_waves, st), "batched anneal launch");
+    return ISING_OK;
+  }
+  // keep the barrier epochs below 2^31 within one launch
+  const bool runahead = a.async_mode && a.async_slack > 0;
+  // (the lock-step top counter reaches epochs x groups, at most 8 groups)
+  const int64_t barriers_per_sweep = g->grid > 1 ? (runahead ? 1 : 8 * std::max(1, a.n_phases)) : 0;
+  int64_t chunk = sweep_end - sweep_begin;
+  if (barriers_per_sweep > 0) chunk = std::max<int64_t>(1, ((int64_t)1 << 30) / barriers_per_sweep);
+  for (int grp = 0; grp < g->n_groups; ++grp) {
+    a.spins = g->d_spins + (size_t)grp * g->n_words;
+    a.flips = g->d_flips + (size_t)grp * 3 * g->n_words;
+    a.r0 = (uint32_t)(grp * g->L);
+    a.r_count = group_r_count(g, grp);
+    for (int64_t t0 = sweep_begin; t0 < sweep_end; t0 += chunk) {
+      a.t_begin = t0;
+      a.t_end = std::min(sweep_end, t0 + chunk);
+      HIP_TRY(launch_fill_u32(g->d_bar + kBarTop, 1, 0u, st), "barrier reset");
+      HIP_TRY(launch_fill_u32(g->d_bar + kBarGroup, kBarFlags + (uint32_t)g->grid - kBarGroup, 0u, st),
+              "barrier reset");
+      HIP_TRY(launch_anneal(g->L, g->lay.enc, g->use_lds, g->res_edges[m], a, g->grid, g->lds_bytes, st),
+              "anneal launch");
+    }
+  }
+  return ISING_OK;
+}
 
 extern "C" {
 
@@ -463,7 +537,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   v = build_layout(csr, g->color, g->n_colors, g->batch ? bin_of.data() : nullptr, n_bins, enc, kmax_for(L, enc),
                    bin_shift, &g->lay, &msg);
   if (v != kPrepOk) return bail(fail((ising_status_t)v, msg));
-  if (!check_layout(g->lay, &msg)) return bail(fail(ISING_ERR_DEVICE, "internal layout check: " + msg));
+  if (!check_layout(g->lay, csr, &msg)) return bail(fail(ISING_ERR_DEVICE, "internal layout check: " + msg));
   HostLayout &lay = g->lay;
   g->L = L;
   g->n_groups = (n_replicas + L - 1) / L;
@@ -490,22 +564,27 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   if ((int64_t)lay.items.size() <= 4 * waves_per_block) grid = 1;  // no grid barriers for tiny graphs
   const int64_t want = env_int("ISING_GRID", 0);
   if (want > 0) grid = (int)std::min<int64_t>(want, max_grid);
+  grid = std::min(grid, kBarMaxGrid);  // the grid barrier polls one flag per workgroup
   g->grid = grid;
   g->nw = grid * waves_per_block;
-  // phase tables: deterministic = one colour class per phase; async merges small classes.
-  // With several workgroups, deterministic phases of at most local_items items
-  // run in workgroup 0 alone, separated by workgroup syncs instead of grid barriers.
-  std::vector<uint32_t> wave_ptr[2], cls_w64[2], own_w64[2], local[2];
-  const int merge_div = (int)env_int("ISING_ASYNC_MERGE", 2);
-  const int64_t local_items = env_int("ISING_LOCAL_ITEMS", 0);  // measured slower on MI355X; off by default
+  // phase tables: deterministic = one colour class per phase; async merges
+  // consecutive classes while the edges inside a phase stay within a budget
+  // (ISING_ASYNC_MERGE, in units of 0.1 % of the edges)
+  std::vector<uint32_t> wave_ptr[2], cls_w64[2], own_w64[2];
+  const double merge_budget = 0.001 * (double)std::max<int64_t>(0, env_int("ISING_ASYNC_MERGE", kAsyncMergeBudget));
   for (int m = 0; m < 2; ++m) {
-    const std::vector<int32_t> pc = phase_classes(lay, class_size, m == 0 ? 0 : merge_div);
+    std::vector<int32_t> pc;
+    if (m == 0) {
+      for (int32_t c = 0; c <= g->n_colors; ++c) pc.push_back(c);
+    } else {
+      try {
+        pc = phase_runs(csr, g->color, g->n_colors, merge_budget);
+      } catch (const std::bad_alloc &) {
+        return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed while building phases"));
+      }
+    }
     g->n_phases[m] = (int32_t)pc.size() - 1;
-    local[m].assign(g->n_phases[m], 0u);
-    if (m == 0 && g->grid > 1)
-      for (int32_t p = 0; p < g->n_phases[m]; ++p)
-        local[m][p] = (int64_t)(lay.phase_items[pc[p + 1]] - lay.phase_items[pc[p]]) <= local_items ? 1u : 0u;
-    wave_ptr[m] = partition_waves(lay, pc, g->nw, local[m], waves_per_block, true);
+    wave_ptr[m] = partition_waves(lay, pc, g->nw, true);
     own_w64[m] = own_words(lay, wave_ptr[m], g->n_phases[m], g->grid, waves_per_block, L);
     // register-resident entries when every wavefront's items fit them
     if (!g->batch && g->use_lds && L == 1 && lay.enc == kEncPm1 && lay.n_slots <= kResMaxSlots &&
@@ -523,14 +602,13 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   // tuner below keeps one of them
   static const int kWaveChoices[3] = {4, 8, 16};
   std::vector<std::vector<uint32_t>> bin_wave_ptrs;
-  std::vector<uint32_t> bin_words, bin_chunks, bin_list;
+  std::vector<uint32_t> bin_words;
   int tune_forced = 0;
   if (g->batch) {
     tune_forced = (int)env_int("ISING_BATCH_WAVES", 0);
     if (tune_forced != 0 && tune_forced != 4 && tune_forced != 8 && tune_forced != 16) tune_forced = 4;
     if (tune_forced == 0 && env_int("ISING_AUTOTUNE", 1) == 0) tune_forced = 4;
     const int32_t nc = g->n_colors;
-    std::vector<uint32_t> none((size_t)nc, 0u);
     bin_words.resize((size_t)n_bins + 1);
     size_t max_words = 0;
     bin_wave_ptrs.resize(3);
@@ -539,7 +617,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
       for (int32_t c = 0; c <= nc; ++c) pc[c] = b * nc + c;
       for (int k = 0; k < 3; ++k) {
         if (tune_forced != 0 && kWaveChoices[k] != tune_forced) continue;
-        const std::vector<uint32_t> wp = partition_waves(lay, pc, kWaveChoices[k], none, kWaveChoices[k], false);
+        const std::vector<uint32_t> wp = partition_waves(lay, pc, kWaveChoices[k], false);
         bin_wave_ptrs[k].insert(bin_wave_ptrs[k].end(), wp.begin(), wp.end());
       }
       bin_words[b] = (uint32_t)((uint64_t)lay.cls_begin[(size_t)b * nc] * L / 32);
@@ -547,41 +625,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
       max_words = std::max<size_t>(max_words, (size_t)(end - bin_words[b]));
     }
     bin_words[n_bins] = (uint32_t)((uint64_t)lay.n_slots * L / 32);
-    // bins whose +-1 entries fit LDS as 2-byte bin-local entries keep them
-    // there for the whole anneal; the rest stream them from HBM each sweep
-    const bool allow_res = lay.enc == kEncPm1 && env_int("ISING_BATCH_RESIDENT", 0) != 0;
-    const uint64_t res_cap = (uint64_t)std::min<int64_t>(kResidentLds, std::max<int64_t>(4096, 1024 * env_int("ISING_RESIDENT_KB", 152)));
-    std::vector<uint32_t> res, other;
-    bin_chunks.assign(2 * (size_t)n_bins, 0u);
-    size_t other_words = 0;
-    g->res_lds = 0;
-    for (int32_t b = 0; b < n_bins; ++b) {
-      const uint32_t i0 = lay.phase_items[(size_t)b * nc], i1 = lay.phase_items[(size_t)(b + 1) * nc];
-      uint64_t c0 = ~0ull, c1 = 0;
-      for (uint32_t i = i0; i < i1; ++i) {
-        const Item &it = lay.items[i];
-        c0 = std::min<uint64_t>(c0, it.base4);
-        c1 = std::max<uint64_t>(c1, (uint64_t)it.base4 + (uint64_t)it.len4 * (64u / it.g));
-      }
-      if (i0 == i1) c0 = c1 = 0;
-      bin_chunks[2 * (size_t)b] = (uint32_t)c0;
-      bin_chunks[2 * (size_t)b + 1] = (uint32_t)c1;
-      const uint64_t words = bin_words[b + 1] - bin_words[b];
-      const uint64_t slots = (uint64_t)(lay.cls_begin[(size_t)(b + 1) * nc] - lay.cls_begin[(size_t)b * nc]);
-      const uint64_t need = ((words + 1) & ~1ull) * 4 + (c1 - c0) * 8;
-      if (allow_res && slots <= kResidentMaxSlots && need <= res_cap) {
-        res.push_back((uint32_t)b);
-        g->res_lds = std::max<size_t>(g->res_lds, (size_t)need);
-      } else {
-        other.push_back((uint32_t)b);
-        other_words = std::max<size_t>(other_words, (size_t)words);
-      }
-    }
-    g->n_res_bins = (int32_t)res.size();
-    bin_list = res;
-    bin_list.insert(bin_list.end(), other.begin(), other.end());
-    g->res_lds = std::max<size_t>(g->res_lds, 16);
-    g->batch_lds = std::max<size_t>(other_words * 4, 16);
+    g->batch_lds = std::max<size_t>(max_words * 4, 16);
   }
 
   // device buffers
@@ -601,10 +645,6 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
     if ((r = dev_alloc(&g->d_wave_ptr[m], sizeof(uint32_t) * wave_ptr[m].size(), "wave table")) != ISING_OK) return bail(r);
     if ((r = upload(g->d_wave_ptr[m], wave_ptr[m].data(), sizeof(uint32_t) * wave_ptr[m].size(), "wave upload")) != ISING_OK)
       return bail(r);
-    if ((r = dev_alloc(&g->d_local[m], sizeof(uint32_t) * (local[m].size() + 1), "local-phase table")) != ISING_OK)
-      return bail(r);
-    if ((r = upload(g->d_local[m], local[m].data(), sizeof(uint32_t) * local[m].size(), "local-phase upload")) != ISING_OK)
-      return bail(r);
     if ((r = dev_alloc(&g->d_own_w64[m], sizeof(uint32_t) * own_w64[m].size(), "ownership table")) != ISING_OK)
       return bail(r);
     if ((r = upload(g->d_own_w64[m], own_w64[m].data(), sizeof(uint32_t) * own_w64[m].size(), "ownership upload")) !=
@@ -621,14 +661,6 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
     if ((r = dev_alloc(&g->d_bin_words, sizeof(uint32_t) * bin_words.size(), "bin word table")) != ISING_OK) return bail(r);
     if ((r = upload(g->d_bin_words, bin_words.data(), sizeof(uint32_t) * bin_words.size(), "bin word upload")) != ISING_OK)
       return bail(r);
-    if ((r = dev_alloc(&g->d_bin_chunks, sizeof(uint32_t) * bin_chunks.size(), "bin chunk table")) != ISING_OK)
-      return bail(r);
-    if ((r = upload(g->d_bin_chunks, bin_chunks.data(), sizeof(uint32_t) * bin_chunks.size(), "bin chunk upload")) !=
-        ISING_OK)
-      return bail(r);
-    if ((r = dev_alloc(&g->d_bin_list, sizeof(uint32_t) * bin_list.size(), "bin list")) != ISING_OK) return bail(r);
-    if ((r = upload(g->d_bin_list, bin_list.data(), sizeof(uint32_t) * bin_list.size(), "bin list upload")) != ISING_OK)
-      return bail(r);
   }
   if ((r = dev_alloc(&g->d_bar, sizeof(uint32_t) * kBarWords, "flags")) != ISING_OK) return bail(r);
   if ((r = dev_alloc(&g->d_cut, sizeof(unsigned long long) * kCutStride * (size_t)n_replicas, "cut")) != ISING_OK)
@@ -641,7 +673,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
       if (kWaveChoices[k] == tune_forced) pick = k;
     if (tune_forced == 0) {
       const TuneKey key{g->lay.n_bins, (int64_t)lay.items.size(), (int64_t)lay.n_slots, g->L, g->n_groups,
-                        lay.enc + 4 * g->n_res_bins, g->batch_lds + (g->res_lds << 20)};
+                        lay.enc, g->batch_lds};
       bool cached = false;
       {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -699,7 +731,15 @@ ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info) {
   info->grid = g->batch ? g->lay.n_bins * g->n_groups : g->grid;
   info->block = g->batch ? 64 * g->batch_waves : kAnnealBlock;
   info->bins = g->batch ? g->lay.n_bins : 0;
-  info->resident_bins = g->batch ? g->n_res_bins : 0;
+  info->max_sweep_gap = 0;
+  if (!g->batch && g->grid > 1) {
+    // read after the work queued on every stream of the device
+    uint32_t gap = 0;
+    DeviceGuard guard(g->device);
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    HIP_TRY(hipMemcpy(&gap, g->d_bar + kBarGap, sizeof gap, hipMemcpyDeviceToHost), "gap readback");
+    info->max_sweep_gap = (int32_t)gap;
+  }
   info->resident_edges = (g->res_edges[0] ? 1 : 0) | (g->res_edges[1] ? 2 : 0);
   info->pm1 = g->lay.enc == kEncPm1 ? 1 : 0;
   info->encoding = g->lay.enc;
@@ -827,82 +867,13 @@ ising_status_t isingGetSpins(ising_graph_t g, int8_t *spins, void *stream) {
 ising_status_t isingAnneal(ising_graph_t g, const ising_schedule_t *s, uint64_t seed, ising_mode_t mode,
                            int64_t sweep_begin, int64_t sweep_end, void *stream) {
   g_last_error.clear();
-  if (g == nullptr || s == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
-  if (mode != ISING_MODE_DETERMINISTIC && mode != ISING_MODE_ASYNC)
-    return fail(ISING_ERR_INVALID_ARGUMENT, "unknown mode");
-  if (s->n_sweeps < 1 || s->n_sweeps > ((int64_t)1 << 32))
-    return fail(ISING_ERR_INVALID_ARGUMENT, "n_sweeps must be in [1, 2^32]");
-  if (s->kind == ISING_SCHED_LINEAR) {
-    if (!(s->p_start >= 0.0 && s->p_start <= 1.0 && s->p_end >= 0.0 && s->p_end <= 1.0))
-      return fail(ISING_ERR_INVALID_ARGUMENT, "probabilities must lie in [0, 1]");
-  } else if (s->kind == ISING_SCHED_EXPLICIT) {
-    if (s->thresholds == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "thresholds is NULL");
-  } else {
-    return fail(ISING_ERR_INVALID_ARGUMENT, "unknown schedule kind");
-  }
-  if (sweep_begin < 0 || sweep_begin > sweep_end || sweep_end > s->n_sweeps)
-    return fail(ISING_ERR_INVALID_ARGUMENT, "need 0 <= sweep_begin <= sweep_end <= n_sweeps");
+  ising_status_t r = internal_check_anneal(g, s, mode, sweep_begin, sweep_end);
+  if (r != ISING_OK) return r;
   if (sweep_begin == sweep_end || g->n == 0) return ISING_OK;
   DeviceGuard guard(g->device);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  ising_status_t r = ensure_thresholds(g, s, st);
-  if (r != ISING_OK) return r;
-
-  AnnealArgs a{};
-  a.entries = reinterpret_cast<const uint4 *>(g->d_entries);
-  a.wts4 = g->d_wts4;
-  a.vid = g->d_vid;
-  a.bias = g->has_field ? g->d_bias : nullptr;
-  a.items = g->d_items;
-  const int m = mode == ISING_MODE_ASYNC ? 1 : 0;
-  a.wave_ptr = g->d_wave_ptr[m];
-  a.own_w64 = g->d_own_w64[m];
-  a.local = g->d_local[m];
-  a.cls_w64 = g->d_cls_w64[m];
-  a.thr = g->d_thr;
-  a.bar = g->d_bar;
-  a.n_words = g->n_words;
-  a.n_phases = g->n_phases[m];
-  a.nw = g->nw;
-  a.async_mode = mode == ISING_MODE_ASYNC ? 1 : 0;
-  a.seed_lo = (uint32_t)seed;
-  a.seed_hi = (uint32_t)(seed >> 32);
-  a.spin_limit = (uint32_t)std::max<int64_t>(1000, env_int("ISING_BARRIER_POLLS", 20000000));
-  a.async_slack = (uint32_t)std::min<int64_t>(8, std::max<int64_t>(0, env_int("ISING_ASYNC_SLACK", 2)));
-  a.bar_flags = env_int("ISING_BARRIER_FLAGS", 0) != 0 && g->grid <= kBarMaxGrid ? 1u : 0u;
-  a.async_refresh = (uint32_t)std::min<int64_t>(64, std::max<int64_t>(1, env_int("ISING_ASYNC_REFRESH", 1)));
-  if (g->batch) {
-    a.spins = g->d_spins;
-    a.flips = g->d_flips;
-    a.wave_ptr = g->d_bin_wave_ptr;
-    a.bin_words = g->d_bin_words;
-    a.n_bins = g->lay.n_bins;
-    a.n_phases = g->n_colors;
-    a.r_total = (uint32_t)g->R;
-    a.t_begin = sweep_begin;
-    a.t_end = sweep_end;
-    HIP_TRY(launch_batch_parts(g, a, g->batch_waves, st), "batched anneal launch");
-    return ISING_OK;
-  }
-  // keep the barrier counter below 2^31 within one launch
-  const int64_t barriers_per_sweep = g->grid > 1 ? (a.async_mode ? 1 : std::max(1, a.n_phases)) : 0;
-  int64_t chunk = sweep_end - sweep_begin;
-  if (barriers_per_sweep > 0) chunk = std::max<int64_t>(1, ((int64_t)1 << 30) / (barriers_per_sweep * g->grid));
-  for (int grp = 0; grp < g->n_groups; ++grp) {
-    a.spins = g->d_spins + (size_t)grp * g->n_words;
-    a.flips = g->d_flips + (size_t)grp * 3 * g->n_words;
-    a.r0 = (uint32_t)(grp * g->L);
-    a.r_count = group_r_count(g, grp);
-    for (int64_t t0 = sweep_begin; t0 < sweep_end; t0 += chunk) {
-      a.t_begin = t0;
-      a.t_end = std::min(sweep_end, t0 + chunk);
-      HIP_TRY(launch_fill_u32(g->d_bar + kBarTop, 1, 0u, st), "barrier reset");
-      HIP_TRY(launch_fill_u32(g->d_bar + kBarGroup, kBarWords - kBarGroup, 0u, st), "barrier reset");
-      HIP_TRY(launch_anneal(g->L, g->lay.enc, g->use_lds, g->res_edges[m], a, g->grid, g->lds_bytes, st),
-              "anneal launch");
-    }
-  }
-  return ISING_OK;
+  if ((r = ensure_thresholds(g, s, st)) != ISING_OK) return r;
+  return internal_anneal(g, seed, mode, sweep_begin, sweep_end, st, g->d_thr, 0);
 }
 
 // Per replica: the sums over directed entries of w s s and of w [s != s],

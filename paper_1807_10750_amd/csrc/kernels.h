@@ -29,9 +29,8 @@ constexpr bool kHasResident = L == 1 && ENC == kEncPm1 && USE_LDS;
 hipError_t launch_anneal(int L, int enc, bool use_lds, bool resident, const AnnealArgs &a, int grid,
                          size_t lds_bytes, hipStream_t s);
 // Batched anneal: grid = n_bins x replica groups, waves per workgroup in {4, 8, 16}.
-// resident: the bins of this launch hold their +-1 entries in LDS (kEncPm1Local).
-hipError_t launch_anneal_batch(int L, int enc, bool resident, int waves, const AnnealArgs &a, int grid,
-                               size_t lds_bytes, hipStream_t s);
+hipError_t launch_anneal_batch(int L, int enc, int waves, const AnnealArgs &a, int grid, size_t lds_bytes,
+                               hipStream_t s);
 hipError_t anneal_occupancy(int L, int enc, bool use_lds, size_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_randomize(int L, uint32_t *spins, const int32_t *vid, uint32_t n_words, uint32_t r0,
                             uint32_t r_count, uint64_t seed, hipStream_t s);

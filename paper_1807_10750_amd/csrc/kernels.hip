@@ -5,17 +5,18 @@
 // given its neighbours (Sec. II-A, Eq. 2, with J = -w so that low energy is
 // a large cut, Sec. III Eq. 4-5), then flips with the sweep's probability F_p
 // (Sec. IV-B, Algorithm 2).  Flip draws come from Philox4x32-10 (Salmon et
-// al., SC'11): replica r of vertex v in sweep t uses word (r mod 4) of the
-// block at counter {v, t, r div 4, 0}, key = seed.
+// al., SC'11): replica r of vertex v in sweep t uses word (t mod 4) of the
+// block at counter {v, t div 4, r, 0}, key = seed, so one block serves four
+// consecutive sweeps.
 //
-// Work is issued colour class by colour class.  In deterministic mode a
-// grid barrier separates the classes, which makes the result equal to a
-// sequential sweep in (colour, id) order.  In async mode there is no wait
-// inside a sweep: each wavefront refreshes its share of a class's spins
-// right after its own items of that class and moves on, so a neighbour's
-// value is from this sweep or the previous one, as in the paper's
-// unsynchronised update.  Every wavefront keeps the loads of its next item
-// in flight while it computes the current one.
+// Work is issued in phases, each a run of colour classes, with a grid
+// barrier after every phase.  In deterministic mode a phase is one class,
+// which makes the result equal to a sequential sweep in (colour, id) order.
+// In async mode a phase merges small classes, so neighbours inside a phase
+// update concurrently and read each other's value from this sweep or the
+// previous one, as in the paper's unsynchronised update; with a run-ahead
+// window there is no barrier inside a sweep at all.  Every wavefront keeps
+// the loads of its next item in flight while it computes the current one.
 //
 // Spin state is an L-bit mask per slot (replica bits) packed in uint32
 // words.  When it fits, each workgroup keeps a copy of the whole state in
@@ -133,28 +134,6 @@ __device__ __forceinline__ void accumulate(int32_t (&c)[L], int32_t &sw, uint32_
   }
 }
 
-// A bin-local entry in the low 16 bits of x (the LDS copy of a resident
-// bin's spins starts at its first slot, so the slot indexes it directly).
-template <int L, typename P>
-__device__ __forceinline__ void accumulate_local(int32_t (&c)[L], uint32_t x, P words) {
-  const uint32_t slot = x & 0x7FFFu;
-  const uint32_t word = words[(slot * L) >> 5];
-  const uint32_t m = L == 1 ? word : word >> ((slot * L) & 31u);
-  const uint32_t off0 = L == 1 ? x : 0u;  // bits [4:0] of x are slot bits [4:0]
-  const uint32_t neg = (x >> 15) & 1u;
-#pragma unroll
-  for (int j = 0; j < L; ++j) c[j] += (int32_t)(__builtin_amdgcn_ubfe(m, off0 + (uint32_t)j, 1u) ^ neg);
-}
-
-template <int L, int ENC, typename P>
-__device__ __forceinline__ void accumulate4(int32_t (&c)[L], int32_t &, const uint2 &x, uint32_t, P words,
-                                            uint32_t) {
-  accumulate_local<L>(c, x.x, words);
-  accumulate_local<L>(c, x.x >> 16, words);
-  accumulate_local<L>(c, x.y, words);
-  accumulate_local<L>(c, x.y >> 16, words);
-}
-
 template <int L, int ENC, typename P>
 __device__ __forceinline__ void accumulate4(int32_t (&c)[L], int32_t &sw, const uint4 &x, uint32_t wv, P words,
                                             uint32_t woff) {
@@ -218,7 +197,7 @@ __device__ __forceinline__ uint32_t draw_flips(int32_t v, uint32_t t, const Anne
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const uint32_t tk = 4u * b + (uint32_t)k;
-    Tk[k] = ((uint32_t)k >= w && (int64_t)tk < a.t_end) ? ro(a.thr, tk) : 0u;
+    Tk[k] = ((uint32_t)k >= w && (int64_t)tk < a.t_end) ? ro(a.thr, (size_t)((int64_t)tk - a.thr_base)) : 0u;
   }
   uint32_t now = 0;
   later[0] = later[1] = later[2] = 0u;
@@ -245,27 +224,41 @@ __device__ __forceinline__ T wave_sum(T x) {
 }
 
 // ---------------------------------------------------------------------------
-// Grid barrier of a cooperative launch: workgroups arrive on one of eight
-// group counters (blockIdx mod 8, i.e. one per XCD), the last arrival of a
-// group bumps the top counter, everybody polls the top counter.  Spin state
-// crosses workgroups only through agent-scope atomics, so with the LDS copy
-// a barrier needs no cache maintenance, only completed stores (s_waitcnt).
-// Without the LDS copy neighbour reads are plain loads and agent fences are
-// used.  A poll limit bounds the wait; hitting it raises the error flag and
-// every workgroup leaves the kernel.
+// Grid barriers of a cooperative launch.  Epochs count from 1.
+//
+// Lock step (deterministic mode, async mode without run-ahead): no
+// workgroup arrives at epoch k + 1 before epoch k is complete, so counters
+// suffice.  Workgroups arrive on one of eight group counters (blockIdx mod
+// 8, one per XCD), the last arrival of a group bumps the top counter, and
+// epoch k is complete when the top counter reaches k times the number of
+// groups.
+//
+// Run-ahead (async_slack >= 1): a workgroup may arrive several epochs ahead
+// of others, so arrivals are per workgroup: workgroup b stores the epoch it
+// reached in its own flag word, and a wait for epoch k has thread t poll
+// flag t until it reads at least k, so an epoch completes only when every
+// workgroup has arrived at it.
+//
+// Spin state crosses workgroups only through agent-scope atomics, so with
+// the LDS copy a barrier needs no cache maintenance, only completed stores
+// (s_waitcnt); without the LDS copy neighbour reads are plain loads and
+// agent fences are used.  A poll limit bounds every wait; hitting it raises
+// the error flag and every workgroup leaves the kernel.
 // ---------------------------------------------------------------------------
-// Barrier epochs count from 1.  Counter tree: epoch k is complete when the
-// top counter reaches k * (number of groups).  Flags: workgroup b stores k in
-// its own word when it arrives, and thread t of every workgroup waits for
-// word t; one store and one load apart instead of three dependent atomics.
-__device__ __forceinline__ void bar_arrive(const AnnealArgs &a, bool fenced, uint32_t epoch) {
+// LDS words of the barrier: the verdict of a wait, the lowest and highest
+// flag it saw, and the largest sweep gap this workgroup has seen.
+struct BarLds {
+  uint32_t ok, lo, hi, gap;
+};
+
+__device__ __forceinline__ void bar_arrive(const AnnealArgs &a, bool fenced, uint32_t epoch, bool flags) {
   if (fenced)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   else
     __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (a.bar_flags) {
+    if (flags) {
       st_coherent(a.bar + kBarFlags + blockIdx.x, epoch);
     } else {
       const uint32_t grp = blockIdx.x & 7u;
@@ -278,35 +271,48 @@ __device__ __forceinline__ void bar_arrive(const AnnealArgs &a, bool fenced, uin
   }
 }
 
-// Waits until every workgroup has arrived at barrier epoch `epoch`.
-// s_ok: one LDS word of the workgroup that carries the verdict to every thread.
-__device__ __forceinline__ bool bar_wait(const AnnealArgs &a, uint32_t epoch, bool fenced, uint32_t &s_ok) {
+// Waits until every workgroup has arrived at barrier epoch `target`, and
+// records in s.gap how many sweeps (of epochs_per_sweep epochs) apart the
+// workgroups were when this one left the wait: with flags, from the highest
+// and lowest flag read; with counters, from how far the top counter had
+// gone past the target.
+__device__ __forceinline__ bool bar_wait(const AnnealArgs &a, uint32_t target, bool fenced, BarLds &s,
+                                         uint32_t epochs_per_sweep, bool flags) {
   uint32_t *bar = a.bar;
   const uint32_t limit = a.spin_limit;
-  if (a.bar_flags) {
-    if (threadIdx.x == 0) s_ok = 1u;
+  if (flags) {
+    if (threadIdx.x == 0) {
+      s.ok = 1u;
+      s.lo = 0xFFFFFFFFu;
+      s.hi = 0u;
+    }
     __syncthreads();
     if (threadIdx.x < gridDim.x) {
-      uint32_t polls = 0;
-      while (ld_coherent(bar + kBarFlags + threadIdx.x) < epoch) {
+      uint32_t polls = 0, f;
+      while ((f = ld_coherent(bar + kBarFlags + threadIdx.x)) < target) {
         if (++polls > limit ||
             ((polls & 63u) == 0u && __hip_atomic_load(bar + kBarErr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
           __hip_atomic_store(bar + kBarErr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          s_ok = 0u;
+          s.ok = 0u;
           break;
         }
         __builtin_amdgcn_s_sleep(1);
       }
+      atomicMin(&s.lo, f);
+      atomicMax(&s.hi, f);
     }
     if (fenced && threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __syncthreads();
-    return __builtin_amdgcn_readfirstlane(s_ok) != 0u;  // wave-uniform, so loops stay scalar
+    if (threadIdx.x == 0 && s.hi > s.lo) {
+      const uint32_t gap = (s.hi - s.lo + epochs_per_sweep - 1u) / epochs_per_sweep;
+      s.gap = gap > s.gap ? gap : s.gap;
+    }
+    return __builtin_amdgcn_readfirstlane(s.ok) != 0u;  // wave-uniform, so loops stay scalar
   }
   const uint32_t n_grp = gridDim.x < 8u ? gridDim.x : 8u;
-  const uint32_t target = epoch * n_grp;
   if (threadIdx.x == 0) {
-    uint32_t ok = 1, polls = 0;
-    while (__hip_atomic_load(bar + kBarTop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    uint32_t ok = 1, polls = 0, top;
+    while ((top = __hip_atomic_load(bar + kBarTop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target * n_grp) {
       if (__hip_atomic_load(bar + kBarErr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++polls > limit) {
         __hip_atomic_store(bar + kBarErr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
@@ -314,31 +320,27 @@ __device__ __forceinline__ bool bar_wait(const AnnealArgs &a, uint32_t epoch, bo
       }
       __builtin_amdgcn_s_sleep(1);
     }
+    if (ok && top > target * n_grp) {
+      // some group already completed a later epoch
+      const uint32_t ahead = (top - target * n_grp + n_grp - 1u) / n_grp;
+      const uint32_t gap = (ahead + epochs_per_sweep - 1u) / epochs_per_sweep;
+      s.gap = gap > s.gap ? gap : s.gap;
+    }
     if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    s_ok = ok;
+    s.ok = ok;
   }
   __syncthreads();
-  return __builtin_amdgcn_readfirstlane(s_ok) != 0u;  // wave-uniform, so loops stay scalar
+  return __builtin_amdgcn_readfirstlane(s.ok) != 0u;  // wave-uniform, so loops stay scalar
 }
 
 // ---------------------------------------------------------------------------
 // Anneal kernel
 // ---------------------------------------------------------------------------
-// One sliced-ELL chunk: four 4-byte entries, or four 2-byte bin-local ones.
-template <int ENC>
-struct ChunkOf {
-  typedef uint4 type;
-};
-template <>
-struct ChunkOf<kEncPm1Local> {
-  typedef uint2 type;
-};
-
 template <int L, int ENC>
 struct Fetched {
   static constexpr int KM = kmax_for(L, ENC);
   static constexpr int KW = ENC == kEncWide ? KM : 1;
-  typename ChunkOf<ENC>::type e[KM];
+  uint4 e[KM];
   uint32_t w[KW];  // separate weights (kEncWide only)
   int32_t vid;
   int32_t bias;    // 2 (-h) + odd-degree bit of this lane's row (external field), 0 without one
@@ -349,15 +351,12 @@ struct Fetched {
 // Issues every load of one item: this lane's row id, its spin word and its
 // share of the sliced-ELL chunks (chunks g, g + G, ...).
 // plane: flip plane to read for this item's sweep (-1 when the sweep draws).
-// lent, c0 (kEncPm1Local only): the bin's entries in LDS and the index of
-// their first chunk in the global stream.
 // RC > 0: the chunks are register-resident; only the row data is loaded.
 template <int L, int ENC, bool FIELD, int RC = 0>
-__device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, int lane, Fetched<L, ENC> &f, int plane,
-                                      const uint2 *lent = nullptr, uint32_t c0 = 0) {
+__device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, int lane, Fetched<L, ENC> &f, int plane) {
   const Item it = uni(it_in);
   constexpr int KM = Fetched<L, ENC>::KM;
-  const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs, K = 64u >> gs;
+  const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs;
   const uint32_t r = (uint32_t)lane >> gs, gl = (uint32_t)lane & (G - 1u);
   const uint32_t slot = it.id + r;
   // the caller id only keys the Philox draws.  With resident state
@@ -378,10 +377,7 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
     const uint32_t q = gl + (uint32_t)k * G;
     if (q < it.len4) {
       const uint32_t idx = (q << ks) + r;
-      if constexpr (ENC == kEncPm1Local)
-        f.e[k] = lent[it.base4 - c0 + idx];
-      else
-        f.e[k] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + idx * 16u);
+      f.e[k] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + idx * 16u);
       if (ENC == kEncWide)
         f.w[k < Fetched<L, ENC>::KW ? k : 0] =
             *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(wblk) + idx * 4u);
@@ -451,13 +447,11 @@ __device__ __forceinline__ void load_resident(const AnnealArgs &a, const Item &i
 template <int L, int ENC, bool USE_LDS, bool FIELD, int RC = 0>
 __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, int lane, const Fetched<L, ENC> &f,
                                         uint32_t *lds, uint32_t t, bool draws, uint32_t woff = 0,
-                                        const uint2 *lent = nullptr, uint32_t c0 = 0, const uint32_t *rw = nullptr,
-                                        ResState *rs = nullptr) {
+                                        const uint32_t *rw = nullptr, ResState *rs = nullptr) {
   static_assert(RC == 0 || L == 1, "resident state holds one replica bit per slot");
   const Item it = uni(it_in);
   constexpr int KM = Fetched<L, ENC>::KM;
-  constexpr bool kPm1 = ENC == kEncPm1 || ENC == kEncPm1Local;
-  typedef typename ChunkOf<ENC>::type Chunk;
+  constexpr bool kPm1 = ENC == kEncPm1;
   const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs, K = 64u >> gs;
   const uint32_t r = (uint32_t)lane >> gs, gl = (uint32_t)lane & (G - 1u);
   const uint32_t slot = it.id + r;
@@ -494,16 +488,13 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   const uint4 *blk = a.entries + it.base4;
   const uint32_t *wblk = ENC == kEncWide ? a.wts4 + it.base4 : nullptr;
   for (uint32_t q0 = gl + (uint32_t)KM * G; RC == 0 && q0 < it.len4; q0 += 4u * G) {
-    Chunk x[4];
+    uint4 x[4];
     uint32_t wv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const uint32_t q = q0 + (uint32_t)k * G;
       const uint32_t idx = ((q < it.len4 ? q : q0) << ks) + r;
-      if constexpr (ENC == kEncPm1Local)
-        x[k] = lent[it.base4 - c0 + idx];
-      else
-        x[k] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + idx * 16u);
+      x[k] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(blk) + idx * 16u);
       wv[k] = ENC == kEncWide ? *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(wblk) + idx * 4u)
                               : 0u;
     }
@@ -637,12 +628,27 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
 }
 
 // Copies spin words [b, e) (64-bit units) from the coherent global state into
-// LDS; the calling threads split the range as (first, stride).
+// LDS; the calling threads split the range as (first, stride).  Each thread
+// issues up to eight loads before it waits, so a refresh of up to 64 KiB per
+// 1024 threads costs one round trip to memory instead of eight.
 __device__ __forceinline__ void restage(const AnnealArgs &a, uint32_t *lds, uint32_t b, uint32_t e,
                                         uint32_t first, uint32_t stride) {
+  constexpr uint32_t kBatch = 8;
   const unsigned long long *g64 = reinterpret_cast<const unsigned long long *>(a.spins);
   unsigned long long *l64 = reinterpret_cast<unsigned long long *>(lds);
-  for (uint32_t i = b + first; i < e; i += stride) l64[i] = ld_coherent64(g64 + i);
+  for (uint32_t i0 = b + first; i0 < e; i0 += kBatch * stride) {
+    unsigned long long v[kBatch];
+#pragma unroll
+    for (uint32_t k = 0; k < kBatch; ++k) {
+      const uint32_t i = i0 + k * stride;
+      v[k] = i < e ? ld_coherent64(g64 + i) : 0ull;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kBatch; ++k) {
+      const uint32_t i = i0 + k * stride;
+      if (i < e) l64[i] = v[k];
+    }
+  }
 }
 
 // RC > 0: each wavefront keeps its items' +-1 entries in registers for the
@@ -650,8 +656,9 @@ __device__ __forceinline__ void restage(const AnnealArgs &a, uint32_t *lds, uint
 template <int L, int ENC, bool USE_LDS, bool FIELD, int RC = 0>
 __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   static_assert(RC == 0 || (USE_LDS && ENC == kEncPm1), "resident entries need the LDS mirror and +-1 entries");
-  // spin mirror, then the barrier verdict word
+  // spin mirror (with the zero word of resident chunks after it)
   __shared__ uint32_t mirror[USE_LDS ? kLdsBudget / 4 + 4 : 4];
+  __shared__ BarLds s_bar;
   uint32_t *const lds = mirror;
   constexpr int kWaves = kAnnealBlock / kWave;
   const int lane = threadIdx.x & (kWave - 1);
@@ -659,16 +666,19 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   const int gw = blockIdx.x * kWaves + wib;
   const bool multi = gridDim.x > 1;
   const bool fenced = !USE_LDS;
-  uint32_t &s_ok = mirror[USE_LDS ? kLdsBudget / 4 : 0];
+  // deterministic mode, and async mode without run-ahead, end every phase
+  // with a grid barrier
+  const bool lockstep = !a.async_mode || a.async_slack == 0u;
   // Pipeline shape that fits the registers: two items in flight (three
   // buffers), one item in flight unrolled, or one item in flight rolled.
   constexpr bool kDeep = ENC == kEncPm1 && L <= 4 && RC == 0;
   constexpr bool kUnrolled = L <= 4 && RC == 0;
+  if (threadIdx.x == 0) s_bar.gap = 0u;
   if (USE_LDS) {
     if (RC > 0 && threadIdx.x == 0) mirror[kZeroWord] = 0u;
     restage(a, lds, 0, a.n_words / 2, threadIdx.x, blockDim.x);
-    __syncthreads();
   }
+  __syncthreads();
   if (a.n_phases <= 0 || a.t_begin >= a.t_end) return;
   const size_t stride = (size_t)a.nw + 1;
   // resident chunks of this wavefront's items, phase by phase in item order
@@ -685,7 +695,6 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   // otherwise its flip bits sit in plane (t mod 4) - 1
   auto plane_of = [&](int64_t t) -> int { return (t == a.t_begin || (t & 3) == 0) ? -1 : (int)(t & 3) - 1; };
   uint32_t epoch = 0;
-  uint32_t run_w = 0;  // first spin word written since the last grid barrier
   uint32_t ib = ro(a.wave_ptr, gw), ie = ro(a.wave_ptr, gw + 1);
   Fetched<L, ENC> fa, fb, fc;
   Item ita;
@@ -717,21 +726,21 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
             fetch<L, ENC, FIELD, RC>(a, itc, lane, fc, plane);
             if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
           if (i + 1 >= ie) break;
           if (i + 3 < ie) {
             ita = pre;
             fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, plane);
             if (i + 4 < ie) pre = ro_item(a.items, i + 4);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
           if (i + 2 >= ie) break;
           if (i + 4 < ie) {
             itb = pre;
             fetch<L, ENC, FIELD, RC>(a, itb, lane, fb, plane);
             if (i + 5 < ie) pre = ro_item(a.items, i + 5);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, itc, lane, fc, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, itc, lane, fc, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
         }
       } else if (kUnrolled) {
         // one item ahead: fa, fb in rotation
@@ -743,14 +752,14 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
             fetch<L, ENC, FIELD, RC>(a, itb, lane, fb, plane);
             if (i + 2 < ie) pre = ro_item(a.items, i + 2);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
           if (i + 1 >= ie) break;
           if (i + 2 < ie) {
             ita = pre;
             fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, plane);
             if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
         }
       } else {
         // one item ahead, rolled: the copy waits for the next item's loads
@@ -761,7 +770,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
             itb = ro_item(a.items, i + 1);
             fetch<L, ENC, FIELD, RC>(a, itb, lane, fb, plane);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, nullptr, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
           if (more) {
             ita = itb;
             fa = fb;
@@ -778,40 +787,37 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
       ib = ro(a.wave_ptr, (size_t)nph * stride + gw);
       ie = ro(a.wave_ptr, (size_t)nph * stride + gw + 1);
       if (done) ie = ib;
-      if (multi && !a.async_mode) {
-        // deterministic.  A run of small phases goes to workgroup 0 alone,
-        // which separates them by workgroup syncs; every other phase, and
-        // the end of such a run, is a grid barrier after which all
-        // workgroups refresh the classes written since the previous one.
-        if (!ro(a.local, ph)) run_w = ro(a.cls_w64, ph);
-        if (ro(a.local, ph) && ro(a.local, nph) && !last_phase) {
-          if (blockIdx.x == 0) {
-            if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          }
-          if (ib < ie) {
-            ita = ro_item(a.items, ib);
-            fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, next_plane);
-          }
-          continue;
-        }
-        bar_arrive(a, fenced, epoch + 1u);
+      if (multi && lockstep) {
+        // A grid barrier ends every phase; after it every workgroup
+        // refreshes its LDS copy of the words the phase wrote.  In
+        // deterministic mode a phase is one colour class, so the sweep
+        // equals the sequential one in (colour, id) order.  In async mode a
+        // phase is a run of classes: a neighbour of an earlier phase is read
+        // at its value of this sweep, a neighbour of a later phase at its
+        // value of the previous sweep, and a neighbour of the same phase at
+        // either (the race of the paper's update; the LDS copy holds its own
+        // workgroup's updates at once and the others' from the previous
+        // barrier on).  No value older than the previous sweep is read.
+        bar_arrive(a, fenced, epoch + 1u, false);
         if (ib < ie) {
           ita = ro_item(a.items, ib);
           fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, next_plane);
         }
         ++epoch;
-        if (!bar_wait(a, epoch, fenced, s_ok)) return;
+        if (!bar_wait(a, epoch, fenced, s_bar, (uint32_t)a.n_phases, false)) return;
         if (USE_LDS) {
-          restage(a, lds, run_w, ro(a.cls_w64, ph + 1), threadIdx.x, blockDim.x);
+          restage(a, lds, ro(a.cls_w64, ph), ro(a.cls_w64, ph + 1), threadIdx.x, blockDim.x);
           __syncthreads();
         }
-        run_w = ro(a.cls_w64, ph + 1);
       } else if (multi) {
-        // async: no wait inside a sweep.  Each wave refreshes its share of
-        // the phase's spin words from the global state, skipping the words
-        // only this workgroup writes (its LDS copy of those is the freshest).
+        // async with run-ahead (async_slack >= 1): no wait inside a sweep.
+        // Each wave refreshes its share of the phase's spin words from the
+        // global state right after its own items of the phase, skipping the
+        // words only this workgroup writes (its LDS copy of those is the
+        // freshest).  A word shared with another workgroup may then lag in
+        // LDS, and a workgroup may run up to async_slack sweeps ahead of
+        // the slowest one, so a neighbour's value can be older than the
+        // previous sweep.
         if (ib < ie) {
           ita = ro_item(a.items, ib);
           fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, next_plane);
@@ -821,8 +827,8 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         // overlaps the other workgroups' work instead of delaying them.
         // The last sweep of the call needs no refresh.
         const bool sweep_end = last_phase && !done;
-        if (sweep_end) bar_arrive(a, fenced, epoch + 1u);
-        if (USE_LDS && !done && (uint64_t)t % a.async_refresh == 0u) {
+        if (sweep_end) bar_arrive(a, fenced, epoch + 1u, true);
+        if (USE_LDS && !done) {
           const size_t oi = ((size_t)ph * gridDim.x + blockIdx.x) * 2;
           const uint32_t o0 = ro(a.own_w64, oi), o1 = ro(a.own_w64, oi + 1);
           const uint32_t b = ro(a.cls_w64, ph), e = ro(a.cls_w64, ph + 1);
@@ -836,10 +842,10 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           }
         }
         if (sweep_end) {
-          // sweeps stay within async_slack of each other: after its sweep
-          // k, a workgroup waits for every workgroup's sweep k - slack
+          // after its sweep k a workgroup waits until every workgroup has
+          // finished sweep k - async_slack
           ++epoch;
-          if (epoch > a.async_slack && !bar_wait(a, epoch - a.async_slack, fenced, s_ok)) return;
+          if (epoch > a.async_slack && !bar_wait(a, epoch - a.async_slack, fenced, s_bar, 1u, true)) return;
         }
       } else {
         // one workgroup: its LDS copy is current
@@ -855,6 +861,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
       }
     }
   }
+  if (threadIdx.x == 0 && s_bar.gap > 0u) atomicMax(a.bar + kBarGap, s_bar.gap);
 }
 
 // ---------------------------------------------------------------------------
@@ -869,7 +876,7 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   extern __shared__ uint32_t lds[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-  const uint32_t bin = ro(args.bin_list, args.list_off + blockIdx.x % (uint32_t)args.n_bins);
+  const uint32_t bin = blockIdx.x % (uint32_t)args.n_bins;
   const uint32_t grp = blockIdx.x / (uint32_t)args.n_bins;
   AnnealArgs a = args;
   a.spins = args.spins + (size_t)grp * args.n_words;
@@ -878,24 +885,6 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   a.r_count = args.r_total - a.r0 < (uint32_t)L ? args.r_total - a.r0 : (uint32_t)L;
   const uint32_t w0 = ro(args.bin_words, bin), w1 = ro(args.bin_words, bin + 1);
   for (uint32_t i = threadIdx.x; i < w1 - w0; i += blockDim.x) lds[i] = ld_coherent(a.spins + w0 + i);
-  // A resident bin reads its entries from HBM once, here, as 2-byte
-  // bin-local entries after its spin words; every sweep then reads LDS.
-  uint2 *lent = nullptr;
-  uint32_t c0 = 0;
-  if constexpr (ENC == kEncPm1Local) {
-    lent = reinterpret_cast<uint2 *>(lds + (((w1 - w0) + 1u) & ~1u));
-    c0 = ro(args.bin_chunks, 2 * (size_t)bin);
-    const uint32_t c1 = ro(args.bin_chunks, 2 * (size_t)bin + 1);
-    const uint32_t slot0 = (uint32_t)(((uint64_t)w0 * 32u) / (uint32_t)L);
-    for (uint32_t i = threadIdx.x; i < c1 - c0; i += blockDim.x) {
-      const uint4 x = args.entries[c0 + i];
-      const uint32_t e0 = ((x.x & ~kSignBit) - slot0) | ((x.x >> 31) << 15);
-      const uint32_t e1 = ((x.y & ~kSignBit) - slot0) | ((x.y >> 31) << 15);
-      const uint32_t e2 = ((x.z & ~kSignBit) - slot0) | ((x.z >> 31) << 15);
-      const uint32_t e3 = ((x.w & ~kSignBit) - slot0) | ((x.w >> 31) << 15);
-      lent[i] = make_uint2(e0 | (e1 << 16), e2 | (e3 << 16));
-    }
-  }
   __syncthreads();
   if (a.n_phases <= 0 || a.t_begin >= a.t_end) return;
   auto plane_of = [&](int64_t t) -> int { return (t == a.t_begin || (t & 3) == 0) ? -1 : (int)(t & 3) - 1; };
@@ -905,7 +894,7 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   Item ita;
   if (ib < ie) {
     ita = ro_item(a.items, ib);
-    fetch<L, ENC, FIELD>(a, ita, lane, fa, plane_of(a.t_begin), lent, c0);
+    fetch<L, ENC, FIELD>(a, ita, lane, fa, plane_of(a.t_begin));
   }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
     const int plane = plane_of(t);
@@ -915,15 +904,15 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
       for (uint32_t i = ib; i < ie; i += 2) {
         if (i + 1 < ie) {
           itb = ro_item(a.items, i + 1);
-          fetch<L, ENC, FIELD>(a, itb, lane, fb, plane, lent, c0);
+          fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
         }
-        compute<L, ENC, true, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, w0, lent, c0);
+        compute<L, ENC, true, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, w0);
         if (i + 1 >= ie) break;
         if (i + 2 < ie) {
           ita = ro_item(a.items, i + 2);
-          fetch<L, ENC, FIELD>(a, ita, lane, fa, plane, lent, c0);
+          fetch<L, ENC, FIELD>(a, ita, lane, fa, plane);
         }
-        compute<L, ENC, true, FIELD>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, w0, lent, c0);
+        compute<L, ENC, true, FIELD>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, w0);
       }
       const bool last_phase = ph + 1 == a.n_phases;
       const int32_t nph = last_phase ? 0 : ph + 1;
@@ -933,7 +922,7 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
       if (done) ie = ib;
       if (ib < ie) {
         ita = ro_item(a.items, ib);
-        fetch<L, ENC, FIELD>(a, ita, lane, fa, last_phase ? plane_of(t + 1) : plane, lent, c0);
+        fetch<L, ENC, FIELD>(a, ita, lane, fa, last_phase ? plane_of(t + 1) : plane);
       }
       if (!a.async_mode || last_phase) __syncthreads();
     }
@@ -1209,8 +1198,7 @@ hipError_t batch_LE(const AnnealArgs &a, int waves, int grid, size_t lds, hipStr
   }
 }
 template <int L>
-hipError_t batch_L(const AnnealArgs &a, int enc, bool resident, int waves, int grid, size_t lds, hipStream_t s) {
-  if (resident) return enc == kEncPm1 ? batch_LE<L, kEncPm1Local>(a, waves, grid, lds, s) : hipErrorInvalidValue;
+hipError_t batch_L(const AnnealArgs &a, int enc, int waves, int grid, size_t lds, hipStream_t s) {
   if (enc == kEncPm1) return batch_LE<L, kEncPm1>(a, waves, grid, lds, s);
   if (enc == kEncW8) return batch_LE<L, kEncW8>(a, waves, grid, lds, s);
   return batch_LE<L, kEncWide>(a, waves, grid, lds, s);
@@ -1276,9 +1264,9 @@ hipError_t launch_anneal(int L, int enc, bool use_lds, bool resident, const Anne
   ISING_DISPATCH_L(L, anneal_L, a, enc, use_lds, resident, grid, lds_bytes, s);
 }
 
-hipError_t launch_anneal_batch(int L, int enc, bool resident, int waves, const AnnealArgs &a, int grid,
-                               size_t lds_bytes, hipStream_t s) {
-  ISING_DISPATCH_L(L, batch_L, a, enc, resident, waves, grid, lds_bytes, s);
+hipError_t launch_anneal_batch(int L, int enc, int waves, const AnnealArgs &a, int grid, size_t lds_bytes,
+                               hipStream_t s) {
+  ISING_DISPATCH_L(L, batch_L, a, enc, waves, grid, lds_bytes, s);
 }
 
 hipError_t anneal_occupancy(int L, int enc, bool use_lds, size_t lds_bytes, int *blocks_per_cu) {

@@ -44,14 +44,8 @@ constexpr uint32_t kSignBit = 0x80000000u;
 
 // Chunks of 4 entries each lane prefetches per item; bounds the degree of a
 // row handled with G lanes to 4 * kmax * G (longer rows loop).
-enum Encoding { kEncPm1 = 0, kEncW8 = 1, kEncWide = 2, kEncPm1Local = 3 };
-// kEncPm1Local exists only inside a batched workgroup whose bin fits LDS:
-// the bin's +-1 entries are copied there once as 2 bytes each, the slot
-// relative to the bin's first slot (15 bits) | sign << 15, two per word.
+enum Encoding { kEncPm1 = 0, kEncW8 = 1, kEncWide = 2 };
 constexpr int kmax_for(int L, int enc) { return (L >= 16 || enc == kEncWide || (enc == kEncW8 && L >= 2)) ? 2 : 4; }
-// LDS a resident bin may use for its spin words and 2-byte entries.
-constexpr uint32_t kResidentLds = 152 * 1024;
-constexpr uint32_t kResidentMaxSlots = 1u << 15;
 
 // One unit of work for one wavefront.
 struct Item {
@@ -62,12 +56,13 @@ struct Item {
 };
 
 // Words of the per-handle flag buffer.
-constexpr int kBarTop = 0;       // barrier epochs completed x groups
+constexpr int kBarTop = 0;       // lock-step barrier: epochs completed x groups
 constexpr int kBarErr = 1;       // set when a barrier poll limit is hit
 constexpr int kBarCheck = 2;     // spin-value check result
-constexpr int kBarGroup = 16;    // group counter k at kBarGroup + 16 * k, k < 8
-constexpr int kBarFlags = 256;   // flag barrier: the epoch workgroup b reached, at kBarFlags + b
-constexpr int kBarMaxGrid = 1024;
+constexpr int kBarGap = 3;       // largest sweep gap between workgroups seen at a barrier
+constexpr int kBarGroup = 16;    // lock-step barrier: group counter k at kBarGroup + 16 * k, k < 8
+constexpr int kBarFlags = 256;   // run-ahead barrier: the epoch workgroup b reached, at kBarFlags + b
+constexpr int kBarMaxGrid = 1024;  // at most one polling thread per workgroup of the grid
 constexpr int kBarWords = kBarFlags + kBarMaxGrid;
 
 // Arguments of the anneal kernel (passed by value).
@@ -83,8 +78,8 @@ struct AnnealArgs {
   uint32_t *spins;           // this replica group's spin words
   uint32_t *flips;           // 3 planes of n_words: flip bits of sweeps 4b+1..4b+3
   const uint32_t *own_w64;   // [n_phases][grid][2] 64-bit spin words only this workgroup writes
-  const uint32_t *local;     // [n_phases] 1: the phase runs in workgroup 0 alone
-  const uint32_t *thr;       // thresholds, indexed by absolute sweep
+  const uint32_t *thr;       // thresholds: sweep t's at thr[t - thr_base]
+  int64_t thr_base;
   uint32_t *bar;             // barrier words (see kBar*), error flag
   uint32_t n_words;          // spin words of the group
   int32_t n_phases;
@@ -95,15 +90,11 @@ struct AnnealArgs {
   uint32_t r0;               // replica index of bit 0
   uint32_t r_count;          // replicas of the group in use (<= L)
   uint32_t spin_limit;       // barrier polls before giving up (error flag)
-  uint32_t bar_flags;        // 1: flag barrier (one word per workgroup), 0: counter tree
   uint32_t async_slack;      // async: sweeps a workgroup may run ahead of the slowest one
-  uint32_t async_refresh;    // async: LDS copies refresh foreign words every this many sweeps
+                             // (0: lock step, a grid barrier after every phase)
   // batched launch only
   const uint32_t *bin_words; // [n_bins + 1] first 32-bit spin word of each bin
-  const uint32_t *bin_chunks;// [n_bins][2] the bin's range of uint4 entry chunks
-  const uint32_t *bin_list;  // bins of this launch at list_off .. list_off + n_bins - 1
-  uint32_t list_off;
-  int32_t n_bins;            // bins of this launch
+  int32_t n_bins;            // bins (workgroups per replica group)
   uint32_t r_total;          // replicas of the handle
 };
 

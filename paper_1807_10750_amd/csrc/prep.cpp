@@ -212,6 +212,13 @@ int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_
     }
     L.n_slots = L.cls_begin[n_cls];
     if (L.n_slots >= (int64_t)0x7FFFFFFF) { *msg = "too many vertices"; return kPrepArg; }
+    // slot | weight << 24 holds slots below 2^24 only; padding classes to 64
+    // slots (per bin) can push the count past it, so the choice is checked
+    // against the final count
+    if (L.enc == kEncW8 && L.n_slots > ((int64_t)1 << 24)) {
+      L.enc = kEncWide;
+      kmax = kmax_for(1, kEncWide);
+    }
     L.vid.assign(L.n_slots, -1);
     L.slot_of.assign(n, -1);
     for (int64_t c = 0; c < n_cls; ++c)
@@ -285,40 +292,58 @@ int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_
   return kPrepOk;
 }
 
-std::vector<int32_t> phase_classes(const HostLayout &L, const std::vector<int64_t> &class_size, int merge_div) {
+std::vector<int32_t> phase_runs(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors,
+                                double budget) {
   std::vector<int32_t> out{0};
-  int64_t total = 0;
-  for (int64_t c : class_size) total += c;
-  const int64_t big = merge_div > 0 ? (total + merge_div - 1) / merge_div : 0;
-  int64_t run = 0;
-  for (int32_t c = 0; c < L.n_phases; ++c) {
-    if (merge_div <= 0 || class_size[c] >= big) {
-      if (run > 0) out.push_back(c);  // close the pending run of small classes
-      out.push_back(c + 1);
-      run = 0;
-      continue;
+  if (n_colors <= 0) {
+    out.push_back(0);
+    return out;
+  }
+  // vertices grouped by colour
+  std::vector<int64_t> start((size_t)n_colors + 1, 0);
+  for (int64_t v = 0; v < g.n; ++v) ++start[(size_t)color[v] + 1];
+  for (int32_t c = 0; c < n_colors; ++c) start[c + 1] += start[c];
+  std::vector<int32_t> byc((size_t)g.n);
+  {
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int64_t v = 0; v < g.n; ++v) byc[(size_t)fill[color[v]]++] = (int32_t)v;
+  }
+  const double limit = budget * (double)(g.nnz / 2);
+  int32_t first = 0;  // first class of the open run
+  int64_t inside = 0; // undirected edges inside the open run
+  for (int32_t c = 1; c < n_colors; ++c) {
+    // edges from class c into the open run's classes (all of them lower)
+    int64_t add = 0;
+    for (int64_t i = start[c]; i < start[c + 1]; ++i) {
+      const int32_t v = byc[(size_t)i];
+      for (int64_t k = g.row_ptr[v]; k < g.row_ptr[v + 1]; ++k) {
+        const int32_t cu = color[g.col[k]];
+        add += (cu >= first && cu < c) ? 1 : 0;
+      }
     }
-    run += class_size[c];
-    if (run >= big) {
-      out.push_back(c + 1);
-      run = 0;
+    if (budget > 0.0 && (double)(inside + add) <= limit) {
+      inside += add;
+    } else {
+      out.push_back(c);
+      first = c;
+      inside = 0;
     }
   }
-  if (out.back() != L.n_phases) out.push_back(L.n_phases);
+  out.push_back(n_colors);
   return out;
 }
 
 std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int32_t> &phase_cls, int32_t nw,
-                                      const std::vector<uint32_t> &local, int32_t local_waves, bool rotate_small) {
+                                      bool rotate_small) {
   const int32_t n_ph = (int32_t)phase_cls.size() - 1;
   std::vector<uint32_t> out((size_t)n_ph * (nw + 1));
   uint64_t rot = 0;
   for (int32_t p = 0; p < n_ph; ++p) {
     const uint32_t b = L.phase_items[phase_cls[p]], e = L.phase_items[phase_cls[p + 1]];
-    const int32_t nwp = local[p] ? std::min(local_waves, nw) : nw;  // waves that share the phase
+    const int32_t nwp = nw;  // waves that share the phase
     uint32_t *o = &out[(size_t)p * (nw + 1)];
     const uint32_t n = e - b;
-    if (rotate_small && !local[p] && n > 0 && n <= (uint32_t)nwp) {
+    if (rotate_small && n > 0 && n <= (uint32_t)nwp) {
       // one item per wavefront, item j on wavefront k + j s: the start k
       // moves from phase to phase so that no wavefront collects the first
       // item of every small phase
@@ -394,7 +419,7 @@ std::vector<uint32_t> own_words(const HostLayout &L, const std::vector<uint32_t>
   return out;
 }
 
-bool check_layout(const HostLayout &L, std::string *msg) {
+bool check_layout(const HostLayout &L, const HostCSR &g, std::string *msg) {
   const uint64_t chunks = L.entries.size() / 4;
   for (size_t i = 0; i < L.items.size(); ++i) {
     const Item &it = L.items[i];
@@ -407,28 +432,39 @@ bool check_layout(const HostLayout &L, std::string *msg) {
       return false;
     }
   }
-  // every entry names a real vertex or is padding on its own row; +-1
-  // padding is pairs of opposite signs plus at most one unsigned entry
+  // Every entry decodes to what the graph says: entry q of a vertex's row is
+  // its q-th CSR neighbour with that weight, every later entry is padding on
+  // its own slot (+-1 padding: pairs of opposite signs plus at most one
+  // unsigned entry), and a padding row holds padding only.
+  std::vector<uint8_t> seen((size_t)L.n_slots, 0);
   for (size_t i = 0; i < L.items.size(); ++i) {
     const Item &it = L.items[i];
     const uint32_t K = 64 / it.g;
     for (uint32_t r = 0; r < K; ++r) {
       const uint32_t own = it.id + r;
+      const int32_t v = L.vid[own];
+      const int64_t deg = v < 0 ? 0 : g.row_ptr[v + 1] - g.row_ptr[v];
+      if (seen[own]++ != 0 || deg > (int64_t)it.len4 * 4) {
+        *msg = "layout row of slot " + std::to_string(own) + " is listed twice or too short";
+        return false;
+      }
       int64_t pad_plus = 0, pad_minus = 0;
       for (uint64_t q = 0; q < (uint64_t)it.len4 * 4; ++q) {
         const uint64_t pos = ((uint64_t)it.base4 + (q / 4) * K + r) * 4 + (q % 4);
         const uint32_t x = L.entries[pos];
         const uint32_t slot = L.enc == kEncPm1 ? (x & ~kSignBit) : (L.enc == kEncW8 ? (x & 0xFFFFFFu) : x);
+        const int32_t wt = L.enc == kEncPm1 ? ((x & kSignBit) ? -1 : 1)
+                                            : (L.enc == kEncW8 ? (int32_t)(int8_t)(x >> 24) : (int32_t)L.wts[pos]);
         bool ok;
-        if (slot == own) {
-          const bool neg = L.enc == kEncPm1 && (x & kSignBit) != 0;
-          (neg ? pad_minus : pad_plus) += 1;
-          ok = L.enc == kEncPm1 || (L.enc == kEncW8 ? (x >> 24) == 0 : L.wts[pos] == 0);
+        if ((int64_t)q < deg) {
+          const int64_t k = g.row_ptr[v] + (int64_t)q;
+          ok = (int64_t)slot < L.n_slots && slot != own && L.vid[slot] == g.col[k] && wt == (int32_t)g.w[k];
         } else {
-          ok = (int64_t)slot < L.n_slots && L.vid[slot] >= 0;
+          ok = slot == own && (L.enc == kEncPm1 || wt == 0);
+          if (ok) (wt < 0 ? pad_minus : pad_plus) += 1;
         }
         if (!ok) {
-          *msg = "layout entry " + std::to_string(pos) + " names a bad slot";
+          *msg = "layout entry " + std::to_string(pos) + " does not match the graph";
           return false;
         }
       }
@@ -438,6 +474,11 @@ bool check_layout(const HostLayout &L, std::string *msg) {
       }
     }
   }
+  for (int64_t s = 0; s < L.n_slots; ++s)
+    if (L.vid[s] >= 0 && !seen[(size_t)s]) {
+      *msg = "layout slot " + std::to_string(s) + " has no row";
+      return false;
+    }
   for (int64_t p = 0; p < (int64_t)L.n_bins * L.n_phases; ++p)
     if (L.cls_begin[p] % 64 != 0 || L.phase_items[p] > L.phase_items[p + 1]) {
       *msg = "layout class table inconsistent";

@@ -62,26 +62,28 @@ int choose_encoding(const HostCSR &g, int64_t n_slots);
 std::vector<int32_t> pack_components(const HostCSR &g, int64_t target, int32_t *n_bins, int64_t *max_comp);
 
 // Classes are (bin, colour) pairs, laid out bin by bin (bin_of = NULL: one
-// bin).  enc: entry encoding; kmax: chunks each lane prefetches (see
-// kmax_for); a row of degree d gets the fewest lanes G with
+// bin).  enc: entry encoding (kEncW8 becomes kEncWide, with its prefetch
+// depth, when the padded slot count exceeds 2^24); kmax: chunks each lane
+// prefetches (see kmax_for); a row of degree d gets the fewest lanes G with
 // d <= (4 * kmax * G) >> bin_shift.
 int build_layout(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors, const int32_t *bin_of,
                  int32_t n_bins, int enc, int kmax, int bin_shift, HostLayout *out, std::string *msg);
 
-// Phases of a sweep as runs of consecutive colour classes: [cls[i], cls[i+1]).
-// Deterministic mode uses one class per phase.  Async mode keeps every class
-// holding at least 1/merge_div of the vertices on its own and merges runs of
-// smaller consecutive classes until they reach that size (merge_div = 0:
-// no merging).
-std::vector<int32_t> phase_classes(const HostLayout &L, const std::vector<int64_t> &class_size, int merge_div);
+// Phases of an async sweep as runs of consecutive colour classes:
+// [out[i], out[i+1]).  A run grows while the undirected edges between its
+// own classes stay at most budget * (nnz / 2); vertices joined by such an
+// edge update in the same phase and read each other's value from this sweep
+// or the previous one.  budget = 0 gives one class per phase, the phases of
+// deterministic mode.
+std::vector<int32_t> phase_runs(const HostCSR &g, const std::vector<int32_t> &color, int32_t n_colors,
+                                double budget);
 
 // Splits each phase's items over nw wavefronts in contiguous runs of about
-// equal cost; a phase with local[p] != 0 goes to the first local_waves
-// wavefronts (one workgroup) only.  rotate_small: a phase with no more items
-// than wavefronts gets one item per wavefront, spaced evenly, from a start
-// that moves from phase to phase.  Returns [n_phases][nw + 1] item offsets.
+// equal cost.  rotate_small: a phase with no more items than wavefronts gets
+// one item per wavefront, spaced evenly, from a start that moves from phase
+// to phase.  Returns [n_phases][nw + 1] item offsets.
 std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int32_t> &phase_cls, int32_t nw,
-                                      const std::vector<uint32_t> &local, int32_t local_waves, bool rotate_small);
+                                      bool rotate_small);
 
 // For each phase and workgroup (waves_per_block consecutive wavefronts), the
 // 64-bit spin words written by that workgroup alone: [lo, hi), or [0, 0).
@@ -96,7 +98,9 @@ uint64_t max_wave_chunks(const HostLayout &L, const std::vector<uint32_t> &wave_
                          uint64_t *max_items);
 
 // Verifies that every item addresses only memory inside the layout (index
-// ranges of entries, slots and spin words).  Returns false with a message.
-bool check_layout(const HostLayout &L, std::string *msg);
+// ranges of entries, slots and spin words) and that every entry decodes to
+// the graph's neighbour and weight at its position.  Returns false with a
+// message.
+bool check_layout(const HostLayout &L, const HostCSR &g, std::string *msg);
 
 }  // namespace ising

@@ -58,7 +58,7 @@ class Info(ctypes.Structure):
                 ("uses_lds", ctypes.c_int32), ("grid", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("pm1", ctypes.c_int32), ("encoding", ctypes.c_int32), ("edge_bytes", ctypes.c_int64),
                 ("vertex_bytes", ctypes.c_int64), ("spin_bytes", ctypes.c_int64),
-                ("items", ctypes.c_int64), ("bins", ctypes.c_int32), ("resident_bins", ctypes.c_int32),
+                ("items", ctypes.c_int64), ("bins", ctypes.c_int32), ("max_sweep_gap", ctypes.c_int32),
                 ("resident_edges", ctypes.c_int32)]
 
     def as_dict(self):

@@ -95,44 +95,13 @@ def test_autotuned_launch_shape(I):
     assert picks[2] == 1024 and picks[3] == 256
 
 
-@pytest.mark.parametrize("knobs", [dict(ISING_BATCH_RESIDENT=1),
-                                   dict(ISING_BATCH_RESIDENT=1, ISING_RESIDENT_KB=8, ISING_BIN_VERTICES=256),
-                                   dict()])
-def test_resident_bins_bit_exact(I, knobs):
-    # small +-1 components: their entries kept in LDS as 2-byte bin-local
-    # entries (all bins, or those under an 8 KB cap), or streamed (default)
-    g = small_batch(50, 12)
-    with env(**knobs):
-        sg, Cg, Eg, so, info = run_both(I, g, 13, 70, 8)
-    if not knobs:
-        assert info["resident_bins"] == 0
-    elif "ISING_RESIDENT_KB" in knobs:
-        assert 0 < info["resident_bins"] < info["bins"]
-    else:
-        assert info["resident_bins"] == info["bins"] >= 2
-    assert np.array_equal(sg, so)
-    C, E = O.cut(g, so)
-    assert np.array_equal(Cg, C) and np.array_equal(Eg, E)
-
-
-def test_resident_and_streamed_bins_in_one_handle(I):
-    # a component too large for LDS streams its entries; the small ones stay resident
-    big = G.erdos_renyi(9000, 48.0 / 8999, "pm1", 21)
-    parts = [big] + G.batched_erdos_renyi(20, 64, 500, 3.0, 12.0, "pm1", 22)
-    g = G.disjoint_union(parts)
-    with env(ISING_BIN_VERTICES=1024, ISING_BATCH_RESIDENT=1):
-        sg, Cg, Eg, so, info = run_both(I, g, 14, 40, 4)
-    assert 0 < info["resident_bins"] < info["bins"]
-    assert np.array_equal(sg, so)
-
-
-def test_resident_bins_with_field_and_replica_packing(I):
+def test_field_and_replica_packing(I):
     g = small_batch(30, 15)
     h = np.random.default_rng(15).integers(-3, 4, g.n).astype(np.int32)
-    with env(ISING_BATCH_L=8, ISING_BATCH_RESIDENT=1):
+    with env(ISING_BATCH_L=8):
         gr = I.Graph.from_csr(g, replicas=8)
     info = gr.info()
-    assert info["resident_bins"] >= 1 and info["replicas_per_group"] == 8
+    assert info["bins"] >= 1 and info["replicas_per_group"] == 8
     gr.set_field(h)
     gr.randomize(16)
     gr.anneal(I.make_schedule(0.1, 0.0, 50), 16, I.MODE_DETERMINISTIC)

@@ -177,8 +177,8 @@ def test_user_spins_and_resume(I):
 
 KNOBS = [dict(ISING_GRID=1), dict(ISING_GRID=3), dict(ISING_GRID=64), dict(ISING_NO_LDS=1),
          dict(ISING_NO_LDS=1, ISING_GRID=5), dict(ISING_BIN_SHIFT=2), dict(ISING_BIN_SHIFT=4, ISING_GRID=2),
-         dict(ISING_BIN_SHIFT=6, ISING_GRID=7), dict(ISING_LOCAL_ITEMS=64), dict(ISING_LOCAL_ITEMS=100000, ISING_GRID=9),
-         dict(ISING_ASYNC_MERGE=1), dict(ISING_BARRIER_FLAGS=1), dict(ISING_BARRIER_FLAGS=1, ISING_NO_LDS=1, ISING_GRID=6)]
+         dict(ISING_BIN_SHIFT=6, ISING_GRID=7), dict(ISING_GRID=9), dict(ISING_ASYNC_MERGE=1),
+         dict(ISING_NO_LDS=1, ISING_GRID=6)]
 
 
 @pytest.mark.parametrize("knobs", KNOBS)

@@ -4,8 +4,8 @@ When every wavefront's items fit the resident registers (+-1 weights, one
 replica bit per slot, LDS copy of the state), the anneal reads the edge
 stream once per call and keeps the entries in registers for all its sweeps.
 Deterministic runs must stay bit-exact to the oracle (Sec. IV-B sweep in
-(colour, id) order) with the registers on and off; async runs keep the
-oracle's cut statistics.  `resident_edges` in the handle's info says which
+(colour, id) order) with the registers on and off; async runs match the
+oracle's cut statistics in both directions.  `resident_edges` in the handle's info says which
 modes use the registers (bit 0 deterministic, bit 1 async).
 """
 import contextlib
@@ -68,7 +68,7 @@ def gpu_det(I, g, seed, M, chunks, knobs, h=None):
         gr.close()
 
 
-KNOBS = [dict(), dict(ISING_GRID=2), dict(ISING_GRID=5), dict(ISING_GRID=64), dict(ISING_BARRIER_FLAGS=1)]
+KNOBS = [dict(), dict(ISING_GRID=2), dict(ISING_GRID=5), dict(ISING_GRID=64), dict(ISING_GRID=200)]
 
 
 @pytest.mark.parametrize("knobs", KNOBS)
@@ -131,6 +131,7 @@ def test_resident_async_cut_statistics(I, name, make, M):
             C, E = O.cut(g, gr.spins())  # the reported cut is the cut of the returned spins
             assert np.array_equal(C, c) and np.array_equal(E, e)
             a.append(float(c[0]))
+        gr_gap = [gr.info()["max_sweep_gap"]]
     finally:
         gr.close()
     a = np.array(a)
@@ -139,6 +140,8 @@ def test_resident_async_cut_statistics(I, name, make, M):
                                     sd, 0, M))[0][0] for sd in seeds], np.float64)
     se = np.sqrt(a.var(ddof=1) / len(a) + o.var(ddof=1) / len(o))
     tol = max(3 * se, 0.005 * o.mean())
+    gap = gr_gap[0]
     print(f"  async mean {a.mean():.1f} sd {a.std():.1f} | oracle mean {o.mean():.1f} sd {o.std():.1f} "
-          f"| tol {tol:.1f}", flush=True)
-    assert a.mean() >= o.mean() - tol
+          f"| diff {a.mean() - o.mean():+.1f} tol {tol:.1f} | gap {gap}", flush=True)
+    assert gap <= 1
+    assert abs(a.mean() - o.mean()) <= tol

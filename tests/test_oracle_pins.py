@@ -481,3 +481,37 @@ def test_validate_overflow_bound():
     st, _, r, _ = O.validate(*_star_csr(k, -128))
     assert st == O.ERR_OVERFLOW and r == 0
     assert O.validate(*_star_csr(k - 1, -128))[0] == O.OK
+
+
+# --------------------------------------------------------------------------
+# Colour-parallel oracle (timing on every host core): no two vertices of a
+# colour class are adjacent, so sweeping a class with many threads at once
+# must give the sequential (colour, id) result bit for bit
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("threads", ["1", "3", "8"])
+def test_colour_parallel_anneal_equals_sequential(threads):
+    script = r"""
+import sys
+import numpy as np
+import oracle as O
+from paper_1807_10750_amd import graphs as G
+cases = [(G.powerlaw_chung_lu(3000, max_deg=200, seed=4), None, 3),
+         (G.erdos_renyi(300, 0.05, "int8", 5), np.random.default_rng(1).integers(-4, 5, 300).astype(np.int32), 2),
+         (G.torus(20, 30), None, 1)]
+for g, h, R in cases:
+    for lf in (False, True):
+        col, nc = O.color(g, lf)
+        T = O.thresholds(0.2, 0.0, 30)
+        s0 = O.init_spins(g.n, R, 11)
+        a = O.anneal(g, O.order(col, nc), s0, T, 11, 0, 30, field=h)
+        b = O.anneal_colour_parallel(g, col, nc, s0, T, 11, 0, 12, field=h)
+        b = O.anneal_colour_parallel(g, col, nc, b, T, 11, 12, 30, field=h)
+        assert np.array_equal(a, b), (g.n, lf)
+print(O.threads())
+"""
+    root = os.path.dirname(HERE)
+    env = dict(os.environ, OMP_NUM_THREADS=threads,
+               PYTHONPATH=os.pathsep.join([root, os.path.join(root, "oracle")]))
+    out = subprocess.run([os.sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == threads

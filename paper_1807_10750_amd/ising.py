@@ -38,7 +38,9 @@ SCHED_EXPLICIT = 1
 EXPORTED = ["isingCreate", "isingRandomizeSpins", "isingSetSpins", "isingAnneal", "isingCut",
             "isingGetSpins", "isingUpdateBest", "isingGetBest", "isingGetColoring", "isingTotalWeight",
             "isingSetField", "isingGetInfo",
-            "isingDestroy", "isingLastError"]
+            "isingDestroy", "isingLastError", "isingAnnealNoAlloc"]
+
+NOALLOC_MAX_SWEEPS = 65536  # ISING_NOALLOC_MAX_SWEEPS (include/ising_noalloc.h)
 
 
 class IsingError(RuntimeError):
@@ -76,6 +78,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "isingRandomizeSpins": [P, u64, P],
         "isingSetSpins": [P, P, P],
         "isingAnneal": [P, ctypes.POINTER(Schedule), u64, c_int, i64, i64, P],
+        "isingAnnealNoAlloc": [P, ctypes.POINTER(Schedule), u64, c_int, i64, i64, P],
         "isingCut": [P, P, P, P],
         "isingGetSpins": [P, P, P],
         "isingUpdateBest": [P, P, P],
@@ -151,6 +154,11 @@ def make_schedule(p_start=0.1, p_end=0.0, n_sweeps=1000, thresholds=None):
 def isingAnneal(h, schedule, seed, mode, sweep_begin, sweep_end, stream=None):
     return _lib.isingAnneal(h, ctypes.byref(schedule), int(seed) & (2**64 - 1), int(mode),
                             int(sweep_begin), int(sweep_end), _stream(stream))
+
+
+def isingAnnealNoAlloc(h, schedule, seed, mode, sweep_begin, sweep_end, stream=None):
+    return _lib.isingAnnealNoAlloc(h, ctypes.byref(schedule), int(seed) & (2**64 - 1), int(mode),
+                                   int(sweep_begin), int(sweep_end), _stream(stream))
 
 
 def isingCut(h, cut, energy=None, stream=None):
@@ -235,6 +243,11 @@ class Graph:
     def anneal(self, schedule, seed, mode=MODE_DETERMINISTIC, sweep_begin=0, sweep_end=None, stream=None):
         end = schedule.n_sweeps if sweep_end is None else sweep_end
         _check(isingAnneal(self._h, schedule, seed, mode, sweep_begin, end, stream), "isingAnneal")
+
+    def anneal_noalloc(self, schedule, seed, mode=MODE_DETERMINISTIC, sweep_begin=0, sweep_end=None, stream=None):
+        """isingAnnealNoAlloc: the same sweeps with no allocation (see include/ising_noalloc.h)."""
+        end = schedule.n_sweeps if sweep_end is None else sweep_end
+        _check(isingAnnealNoAlloc(self._h, schedule, seed, mode, sweep_begin, end, stream), "isingAnnealNoAlloc")
 
     def cut(self, stream=None):
         """(cut int64 [R], energy int64 [R]) as numpy arrays."""

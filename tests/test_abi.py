@@ -5,11 +5,11 @@ import os
 import re
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ising.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("ising.h", "ising_noalloc.h")]
 
 
 def declared():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"^\s*(?:ising_status_t|const char \*)\s*(ising[A-Za-z]+)\s*\(", text, re.M)))
 
 

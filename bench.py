@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--coloring", default="lf", choices=["ff", "lf"])
     ap.add_argument("--sweeps", type=int, default=None, help="override the schedule length")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle time (0 = skip)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of the step captured in a HIP graph (anneal_ms is then the whole step)")
     ap.add_argument("--no-extra", dest="extra", action="store_false",
                     help="skip the run-ahead and deterministic context legs")
     ap.add_argument("--p-start", type=float, default=0.1, help="initial flip probability of the linear schedule")
@@ -319,7 +321,28 @@ def main():
         torch.cuda.synchronize()
         return t_start.elapsed_time(t_end), [x.elapsed_time(y) for x, y in ev]
 
-    total_ms, anneal_ms = timed_anneals(args.steps, sch, mode, 2000)
+    if args.graph:
+        # the whole step (randomize, anneal, cut into device memory) captured
+        # once in a HIP graph and replayed; the multi-workgroup anneal is then
+        # an ordinary kernel node instead of a cooperative launch
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step(0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        t_start.record(stream)
+        for _ in range(args.steps):
+            graph.replay()
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        total_ms = t_start.elapsed_time(t_end)
+        anneal_ms = [total_ms / args.steps]  # whole steps: the anneal dominates
+    else:
+        total_ms, anneal_ms = timed_anneals(args.steps, sch, mode, 2000)
     cuts = cut.cpu().numpy()
     ms_step = total_ms / args.steps
     value = g.n * R * M * args.steps / (total_ms / 1e3)

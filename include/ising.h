@@ -204,6 +204,16 @@ ising_status_t isingTotalWeight(ising_graph_t g, int64_t *W);
  * the old field); not for use under graph capture. */
 ising_status_t isingSetField(ising_graph_t g, const int32_t *h, void *stream);
 
+/* Per-vertex flip temperature (not in the paper, which uses one F_p for
+ * every spin; it lets the learned warm start of ising_warm.h say how much
+ * each vertex should be shaken): uint8 [n] multipliers m_v in [0, 15], caller
+ * ids, host or device pointer, copied.  Vertex v then flips in sweep t iff
+ * its draw x < min(2^32 - 1, floor(T[t] * m_v / 8)); m = 8 everywhere is the
+ * plain anneal, m = 0 never flips.  NULL removes the multipliers.  A value
+ * above 15 gives ISING_ERR_INVALID_ARGUMENT and leaves them unchanged.
+ * Synchronises the stream first; not for use under graph capture. */
+ising_status_t isingSetFlipScale(ising_graph_t g, const uint8_t *scale, void *stream);
+
 /* Layout and launch facts of a handle, for benchmarks and tests. */
 typedef struct {
   int64_t n_slots;          /* vertices after padding each colour class to a multiple of 64 */

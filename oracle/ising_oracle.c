@@ -46,6 +46,11 @@
  *       H = sum_{u<v} w_uv s_u s_v - sum_v h_v s_v.  The cut ignores h.
  *       h is int32 and every row must keep sum |w| + |h_v| <= 2^30 - 1, which
  *       leaves headroom for exact integer arithmetic on 2 h.
+ *   R15 Per-vertex flip temperature (not in the paper; it only lets a learned
+ *       warm start choose how much each vertex is shaken): vertex v flips
+ *       in sweep t iff its draw x < min(2^32 - 1, floor(T_t * m_v / 8))
+ *       for an integer multiplier m_v in [0, 15]; m = 8 everywhere is the
+ *       plain anneal, m = 0 never flips that vertex.  scale == NULL is m = 8.
  *   R12 The deterministic ("coloured") schedule: vertices are visited in
  *       (colour, id) order of a greedy colouring, sequentially.  Because no
  *       two vertices of one colour are adjacent, any order inside a colour
@@ -293,6 +298,13 @@ void oracle_init_spins(int64_t n, int32_t R, uint64_t seed, int8_t *spins) {
     }
 }
 
+/* Flip threshold of vertex v in a sweep with threshold T (R15). */
+static uint32_t vertex_threshold(uint32_t T, const uint8_t *scale, int64_t v) {
+  if (scale == NULL) return T;
+  uint64_t x = ((uint64_t)T * (uint64_t)scale[v]) >> 3;
+  return x > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)x;
+}
+
 /* Local field h_v = sum_u w_vu s_u (Eq. 2 with J = -w, reading R1). */
 static int32_t local_field(int64_t v, const int64_t *row_ptr, const int32_t *col, const int8_t *w,
                            const int8_t *s) {
@@ -331,8 +343,8 @@ static int8_t field_update(int64_t v, const int64_t *row_ptr, const int32_t *col
 /* schedule (indexed by absolute sweep).                                    */
 /* ------------------------------------------------------------------------ */
 int oracle_anneal(int64_t n, const int64_t *row_ptr, const int32_t *col, const int8_t *w,
-                  const int32_t *field, const int32_t *order, int32_t R, int8_t *spins, const uint32_t *T,
-                  uint64_t seed, int64_t t_begin, int64_t t_end) {
+                  const int32_t *field, const uint8_t *scale, const int32_t *order, int32_t R, int8_t *spins,
+                  const uint32_t *T, uint64_t seed, int64_t t_begin, int64_t t_end) {
   if (t_begin < 0 || t_end < t_begin) return OR_ERR_ARG;
   for (int32_t r = 0; r < R; ++r) {
     int8_t *s = spins + (int64_t)r * n;
@@ -340,7 +352,8 @@ int oracle_anneal(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
       for (int64_t i = 0; i < n; ++i) {
         int64_t v = order[i];
         s[v] = field_update(v, row_ptr, col, w, field, s, s[v]);
-        if (flip_draw((uint32_t)v, (uint32_t)t, (uint32_t)r, seed) < T[t]) s[v] = (int8_t)-s[v];
+        if (flip_draw((uint32_t)v, (uint32_t)t, (uint32_t)r, seed) < vertex_threshold(T[t], scale, v))
+          s[v] = (int8_t)-s[v];
       }
     }
   }
@@ -355,7 +368,8 @@ int oracle_anneal(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
 /* bit, whatever the thread count.  Used to time the oracle on every core.  */
 /* ------------------------------------------------------------------------ */
 int oracle_anneal_colour_parallel(int64_t n, const int64_t *row_ptr, const int32_t *col, const int8_t *w,
-                                  const int32_t *field, const int32_t *order, const int32_t *color,
+                                  const int32_t *field, const uint8_t *scale, const int32_t *order,
+                                  const int32_t *color,
                                   int32_t n_colors, int32_t R, int8_t *spins, const uint32_t *T, uint64_t seed,
                                   int64_t t_begin, int64_t t_end) {
   if (t_begin < 0 || t_end < t_begin || n_colors < 0) return OR_ERR_ARG;
@@ -372,7 +386,8 @@ int oracle_anneal_colour_parallel(int64_t n, const int64_t *row_ptr, const int32
         for (int64_t i = first[c]; i < first[c + 1]; ++i) {
           int64_t v = order[i];
           int8_t x = field_update(v, row_ptr, col, w, field, s, s[v]);
-          if (flip_draw((uint32_t)v, (uint32_t)t, (uint32_t)r, seed) < T[t]) x = (int8_t)-x;
+          if (flip_draw((uint32_t)v, (uint32_t)t, (uint32_t)r, seed) < vertex_threshold(T[t], scale, v))
+            x = (int8_t)-x;
           s[v] = x;
         }
       }

@@ -46,9 +46,9 @@ def lib():
         L.oracle_order.restype = None
         L.oracle_init_spins.argtypes = [i64, i32, u64, P]
         L.oracle_init_spins.restype = None
-        L.oracle_anneal.argtypes = [i64, P, P, P, P, P, i32, P, P, u64, i64, i64]
+        L.oracle_anneal.argtypes = [i64, P, P, P, P, P, P, i32, P, P, u64, i64, i64]
         L.oracle_anneal_jacobi.argtypes = [i64, P, P, P, P, i32, P, P, u64, i64, i64]
-        L.oracle_anneal_colour_parallel.argtypes = [i64, P, P, P, P, P, P, i32, i32, P, P, u64, i64, i64]
+        L.oracle_anneal_colour_parallel.argtypes = [i64, P, P, P, P, P, P, P, i32, i32, P, P, u64, i64, i64]
         L.oracle_threads.argtypes = []
         L.oracle_cut.argtypes = [i64, P, P, P, P, i32, P, P, P]
         L.oracle_validate_field.argtypes = [i64, P, P, P, P]
@@ -135,10 +135,20 @@ def _field(g, field):
     return f if g.n else np.zeros(1, np.int32)
 
 
-def anneal(g, order_arr, spins, T, seed: int, t_begin: int, t_end: int, field=None) -> np.ndarray:
+def _scale(g, scale):
+    """uint8 [n] flip-temperature multipliers in [0, 15] (None: 8 everywhere, the plain anneal)."""
+    if scale is None:
+        return None
+    m = np.ascontiguousarray(scale, dtype=np.uint8)
+    assert m.shape == (g.n,) and (m <= 15).all()
+    return m if g.n else np.zeros(1, np.uint8)
+
+
+def anneal(g, order_arr, spins, T, seed: int, t_begin: int, t_end: int, field=None, scale=None) -> np.ndarray:
     """Deterministic sequential anneal in the given visiting order.  Returns new spins."""
     rp, c, w = _csr(g)
     f = _field(g, field)
+    m = _scale(g, scale)
     s = np.array(spins, dtype=np.int8, copy=True, order="C")
     R = s.shape[0]
     o = np.ascontiguousarray(order_arr, dtype=np.int32)
@@ -149,26 +159,28 @@ def anneal(g, order_arr, spins, T, seed: int, t_begin: int, t_end: int, field=No
         TT = np.zeros(1, np.uint32)
     if s.size == 0:
         return s
-    st = lib().oracle_anneal(g.n, _p(rp), _p(c), _p(w), _p(f), _p(o), R, _p(s), _p(TT), seed, t_begin, t_end)
+    st = lib().oracle_anneal(g.n, _p(rp), _p(c), _p(w), _p(f), _p(m), _p(o), R, _p(s), _p(TT), seed, t_begin, t_end)
     if st != OK:
         raise RuntimeError(f"oracle_anneal status {st}")
     return s
 
 
 def anneal_colour_parallel(g, color_arr, n_colors, spins, T, seed: int, t_begin: int, t_end: int,
-                           field=None) -> np.ndarray:
+                           field=None, scale=None) -> np.ndarray:
     """The deterministic anneal with each colour class swept by all host threads (OpenMP).
 
     Equal, bit for bit, to ``anneal`` in (colour, id) order."""
     rp, c, w = _csr(g)
     f = _field(g, field)
+    m = _scale(g, scale)
     s = np.array(spins, dtype=np.int8, copy=True, order="C")
     if s.size == 0:
         return s
     ca = np.ascontiguousarray(color_arr, dtype=np.int32)
     o = order(ca, n_colors)
     TT = np.ascontiguousarray(T, dtype=np.uint32)
-    st = lib().oracle_anneal_colour_parallel(g.n, _p(rp), _p(c), _p(w), _p(f), _p(o), _p(ca), n_colors, s.shape[0],
+    st = lib().oracle_anneal_colour_parallel(g.n, _p(rp), _p(c), _p(w), _p(f), _p(m), _p(o), _p(ca), n_colors,
+                                             s.shape[0],
                                              _p(s), _p(TT), seed, t_begin, t_end)
     if st != OK:
         raise RuntimeError(f"oracle_anneal_colour_parallel status {st}")

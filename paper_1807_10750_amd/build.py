@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libising.so")
-SOURCES = ["prep.cpp", "api.cpp", "kernels.hip", "warm.hip", "noalloc.hip"]
+SOURCES = ["prep.cpp", "api.cpp", "kernels.hip", "warm.hip", "mpnn.hip", "noalloc.hip"]
 ARCH = os.environ.get("ISING_OFFLOAD_ARCH", "gfx950")
 
 

@@ -101,7 +101,7 @@ struct ising_graph_s {
   uint32_t *d_wts4 = nullptr;
   int32_t *d_vid = nullptr;
   Item *d_items = nullptr;
-  uint32_t *d_wave_ptr[2] = {nullptr, nullptr};  // per mode: [phases][nw + 1]
+  uint32_t *d_wave_ptr[2] = {nullptr, nullptr};  // per mode: [phases][nw][2] item ranges
   uint32_t *d_own_w64[2] = {nullptr, nullptr};   // per mode: [phases][grid][2]
   uint32_t *d_flips = nullptr;                   // 3 flip planes per replica group
   // batched mode: one workgroup per (bin of whole components, replica group)
@@ -124,6 +124,9 @@ struct ising_graph_s {
   std::vector<uint32_t> degree;
   int32_t *d_bias = nullptr;
   bool has_field = false;
+  // per-vertex flip-temperature multipliers per slot (isingSetFlipScale)
+  uint8_t *d_scale = nullptr;
+  bool has_scale = false;
   // best-of-run state (isingUpdateBest): best cut per replica, the spins it
   // was seen with, per-group improvement masks, a scratch cut array
   int64_t *d_best_cut = nullptr;
@@ -159,7 +162,7 @@ void free_all(ising_graph_s *g) {
                   g->d_cls_w64[0], g->d_cls_w64[1], g->d_own_w64[0], g->d_own_w64[1], g->d_flips,
                   g->d_bin_wave_ptr, g->d_bin_words,
                   g->d_spins, g->d_thr, g->d_bar, g->d_cut, g->d_stage, g->d_bias,
-                  g->d_best_cut, g->d_best_spins, g->d_best_mask, g->d_cutvals};
+                  g->d_best_cut, g->d_best_spins, g->d_best_mask, g->d_cutvals, g->d_scale};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (g->h_thr) (void)hipHostFree(g->h_thr);
@@ -368,6 +371,7 @@ ising_status_t internal_anneal(ising_graph_t g, uint64_t seed, ising_mode_t mode
   a.wts4 = g->d_wts4;
   a.vid = g->d_vid;
   a.bias = g->has_field ? g->d_bias : nullptr;
+  a.scale = g->has_scale ? g->d_scale : nullptr;
   a.items = g->d_items;
   const int m = mode == ISING_MODE_ASYNC ? 1 : 0;
   a.wave_ptr = g->d_wave_ptr[m];
@@ -584,7 +588,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
       }
     }
     g->n_phases[m] = (int32_t)pc.size() - 1;
-    wave_ptr[m] = partition_waves(lay, pc, g->nw, true);
+    wave_ptr[m] = rotate_ranges(partition_waves(lay, pc, g->nw, true), g->n_phases[m], g->nw, waves_per_block);
     own_w64[m] = own_words(lay, wave_ptr[m], g->n_phases[m], g->grid, waves_per_block, L);
     // register-resident entries when every wavefront's items fit them
     if (!g->batch && g->use_lds && L == 1 && lay.enc == kEncPm1 && lay.n_slots <= kResMaxSlots &&
@@ -788,6 +792,31 @@ ising_status_t isingSetField(ising_graph_t g, const int32_t *h, void *stream) {
     return r;
   if ((r = upload(g->d_bias, bias.data(), sizeof(int32_t) * bias.size(), "field upload")) != ISING_OK) return r;
   g->has_field = true;
+  return ISING_OK;
+}
+
+ising_status_t isingSetFlipScale(ising_graph_t g, const uint8_t *scale, void *stream) {
+  g_last_error.clear();
+  if (g == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL handle");
+  DeviceGuard guard(g->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // anneals already queued on the stream may still read the old multipliers
+  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+  if (scale == nullptr) {
+    g->has_scale = false;
+    return ISING_OK;
+  }
+  std::vector<uint8_t> m;
+  ising_status_t r = fetch(&m, scale, g->n, "flip scale");
+  if (r != ISING_OK) return r;
+  for (int64_t v = 0; v < g->n; ++v)
+    if (m[(size_t)v] > 15)
+      return fail(ISING_ERR_INVALID_ARGUMENT, "vertex " + std::to_string(v) + ": flip scale above 15");
+  std::vector<uint8_t> per_slot((size_t)g->lay.n_slots, 0);
+  for (int64_t v = 0; v < g->n; ++v) per_slot[(size_t)g->lay.slot_of[(size_t)v]] = m[(size_t)v];
+  if (g->d_scale == nullptr && (r = dev_alloc(&g->d_scale, per_slot.size(), "flip scale")) != ISING_OK) return r;
+  if ((r = upload(g->d_scale, per_slot.data(), per_slot.size(), "flip scale upload")) != ISING_OK) return r;
+  g->has_scale = true;
   return ISING_OK;
 }
 

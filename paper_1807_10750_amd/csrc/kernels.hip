@@ -190,14 +190,25 @@ __device__ __forceinline__ uint32_t update_mask(const int32_t (&h)[L], uint32_t 
 // Flip draws of sweep t (reading: word t mod 4 of the Philox block at counter
 // {v, t div 4, r, 0}).  Returns this sweep's flip bits; the bits of the
 // block's later sweeps t' < t_end are returned in later[0..2] (index t' mod 4 - 1).
+// With a per-vertex flip temperature, slot's threshold is min(2^32 - 1,
+// floor(T m / 8)) for its multiplier m.
 template <int L>
-__device__ __forceinline__ uint32_t draw_flips(int32_t v, uint32_t t, const AnnealArgs &a, uint32_t (&later)[3]) {
+__device__ __forceinline__ uint32_t draw_flips(int32_t v, uint32_t slot, uint32_t t, const AnnealArgs &a,
+                                               uint32_t (&later)[3]) {
   const uint32_t b = t >> 2, w = t & 3u;
   uint32_t Tk[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const uint32_t tk = 4u * b + (uint32_t)k;
     Tk[k] = ((uint32_t)k >= w && (int64_t)tk < a.t_end) ? ro(a.thr, (size_t)((int64_t)tk - a.thr_base)) : 0u;
+  }
+  if (a.scale != nullptr) {
+    const uint64_t m = a.scale[slot];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint64_t x = ((uint64_t)Tk[k] * m) >> 3;
+      Tk[k] = x > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)x;
+    }
   }
   uint32_t now = 0;
   later[0] = later[1] = later[2] = 0u;
@@ -536,7 +547,7 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   uint32_t later[3];
   uint32_t flips;
   if (draws)
-    flips = draw_flips<L>(RC > 0 ? a.vid[slot] : f.vid, t, a, later);
+    flips = draw_flips<L>(RC > 0 ? a.vid[slot] : f.vid, slot, t, a, later);
   else if (RC > 0)
     flips = (rs->flip >> (3u * rs->j + (t & 3u) - 1u)) & 1u;  // sweep t's plane is (t mod 4) - 1
   else
@@ -680,14 +691,15 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   }
   __syncthreads();
   if (a.n_phases <= 0 || a.t_begin >= a.t_end) return;
-  const size_t stride = (size_t)a.nw + 1;
+  // item range of (phase, wavefront): wave_ptr[2 (phase * nw + gw)] .. [+ 1]
+  auto range_at = [&](int32_t ph) -> size_t { return ((size_t)ph * (size_t)a.nw + (size_t)gw) * 2; };
   // resident chunks of this wavefront's items, phase by phase in item order
   // (the order the sweeps visit them); cr is the next chunk's register
   uint32_t rw[RC > 0 ? 3 * RC : 3] = {};
   ResState rs{0u, 0u, 0u, 0u, 0u, 0u};
   if constexpr (RC > 0) {
     for (int32_t ph = 0; ph < a.n_phases; ++ph) {
-      const uint32_t b = ro(a.wave_ptr, (size_t)ph * stride + gw), e = ro(a.wave_ptr, (size_t)ph * stride + gw + 1);
+      const uint32_t b = ro(a.wave_ptr, range_at(ph)), e = ro(a.wave_ptr, range_at(ph) + 1);
       for (uint32_t i = b; i < e; ++i) load_resident<RC>(a, ro_item(a.items, i), lane, rw, rs);
     }
   }
@@ -695,7 +707,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   // otherwise its flip bits sit in plane (t mod 4) - 1
   auto plane_of = [&](int64_t t) -> int { return (t == a.t_begin || (t & 3) == 0) ? -1 : (int)(t & 3) - 1; };
   uint32_t epoch = 0;
-  uint32_t ib = ro(a.wave_ptr, gw), ie = ro(a.wave_ptr, gw + 1);
+  uint32_t ib = ro(a.wave_ptr, range_at(0)), ie = ro(a.wave_ptr, range_at(0) + 1);
   Fetched<L, ENC> fa, fb, fc;
   Item ita;
   if (ib < ie) {
@@ -784,8 +796,8 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
       const int32_t nph = last_phase ? 0 : ph + 1;
       const bool done = last_phase && t + 1 == a.t_end;
       const int next_plane = last_phase ? plane_of(t + 1) : plane;
-      ib = ro(a.wave_ptr, (size_t)nph * stride + gw);
-      ie = ro(a.wave_ptr, (size_t)nph * stride + gw + 1);
+      ib = ro(a.wave_ptr, range_at(nph));
+      ie = ro(a.wave_ptr, range_at(nph) + 1);
       if (done) ie = ib;
       if (multi && lockstep) {
         // A grid barrier ends every phase; after it every workgroup

@@ -72,8 +72,11 @@ struct AnnealArgs {
   const int32_t *vid;        // slot -> caller vertex id, -1 for padding
   const int32_t *bias;       // slot -> 2 (-h) + (degree odd, +-1 encoding) of the external
                              // field (nullptr: no field); see kernels.hip compute()
+  const uint8_t *scale;      // slot -> flip-temperature multiplier m in [0, 15]: the slot flips
+                             // iff its draw < min(2^32 - 1, T m / 8) (nullptr: m = 8)
   const Item *items;         // all items, phase by phase
-  const uint32_t *wave_ptr;  // [n_phases][nw + 1] item ranges per global wavefront
+  const uint32_t *wave_ptr;  // cooperative: [n_phases][nw][2] item range (begin, end) of each
+                             // wavefront; batched: [bins][phases][waves + 1] prefix offsets
   const uint32_t *cls_w64;   // [n_phases + 1] class boundaries in 64-bit words of the spin state
   uint32_t *spins;           // this replica group's spin words
   uint32_t *flips;           // 3 planes of n_words: flip bits of sweeps 4b+1..4b+3

@@ -380,13 +380,30 @@ std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int
   return out;
 }
 
-uint64_t max_wave_chunks(const HostLayout &L, const std::vector<uint32_t> &wave_ptr, int32_t n_ph, int32_t nw,
+std::vector<uint32_t> rotate_ranges(const std::vector<uint32_t> &prefix, int32_t n_ph, int32_t nw,
+                                    int32_t waves_per_block) {
+  std::vector<uint32_t> out((size_t)n_ph * nw * 2);
+  const int32_t grid = std::max(1, nw / std::max(1, waves_per_block));
+  for (int32_t p = 0; p < n_ph; ++p) {
+    // phase p starts at workgroup rot, so phases spread their heads
+    const int32_t rot = (int32_t)(((int64_t)p * grid) / std::max(1, n_ph)) * waves_per_block;
+    const uint32_t *o = &prefix[(size_t)p * (nw + 1)];
+    for (int32_t w = 0; w < nw; ++w) {
+      const int32_t j = ((w - rot) % nw + nw) % nw;
+      out[((size_t)p * nw + w) * 2] = o[j];
+      out[((size_t)p * nw + w) * 2 + 1] = o[j + 1];
+    }
+  }
+  return out;
+}
+
+uint64_t max_wave_chunks(const HostLayout &L, const std::vector<uint32_t> &ranges, int32_t n_ph, int32_t nw,
                          uint64_t *max_items) {
   uint64_t most = 0, items = 0;
   for (int32_t w = 0; w < nw; ++w) {
     uint64_t sum = 0, cnt = 0;
     for (int32_t p = 0; p < n_ph; ++p)
-      for (uint32_t i = wave_ptr[(size_t)p * (nw + 1) + w]; i < wave_ptr[(size_t)p * (nw + 1) + w + 1]; ++i) {
+      for (uint32_t i = ranges[((size_t)p * nw + w) * 2]; i < ranges[((size_t)p * nw + w) * 2 + 1]; ++i) {
         sum += (L.items[i].len4 + L.items[i].g - 1) / L.items[i].g;
         ++cnt;
       }
@@ -397,14 +414,15 @@ uint64_t max_wave_chunks(const HostLayout &L, const std::vector<uint32_t> &wave_
   return most;
 }
 
-std::vector<uint32_t> own_words(const HostLayout &L, const std::vector<uint32_t> &wave_ptr, int32_t n_ph,
+std::vector<uint32_t> own_words(const HostLayout &L, const std::vector<uint32_t> &ranges, int32_t n_ph,
                                 int32_t grid, int32_t waves_per_block, int Lbits) {
   std::vector<uint32_t> out((size_t)n_ph * grid * 2, 0);
   const int32_t nw = grid * waves_per_block;
   for (int32_t p = 0; p < n_ph; ++p)
     for (int32_t g = 0; g < grid; ++g) {
-      const uint32_t i0 = wave_ptr[(size_t)p * (nw + 1) + (size_t)g * waves_per_block];
-      const uint32_t i1 = wave_ptr[(size_t)p * (nw + 1) + (size_t)(g + 1) * waves_per_block];
+      // the workgroup's waves hold consecutive item ranges (rotation moves whole workgroups)
+      const uint32_t i0 = ranges[((size_t)p * nw + (size_t)g * waves_per_block) * 2];
+      const uint32_t i1 = ranges[((size_t)p * nw + (size_t)(g + 1) * waves_per_block - 1) * 2 + 1];
       uint32_t *o = &out[((size_t)p * grid + g) * 2];
       if (i0 >= i1) continue;
       const Item &f = L.items[i0], &l = L.items[i1 - 1];

@@ -85,16 +85,26 @@ std::vector<int32_t> phase_runs(const HostCSR &g, const std::vector<int32_t> &co
 std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int32_t> &phase_cls, int32_t nw,
                                       bool rotate_small);
 
+// The per-wavefront item ranges of the cooperative anneal, [n_ph][nw][2]
+// (begin, end), from a prefix table of partition_waves: phase p's ranges
+// are rotated by a whole number of workgroups, about p * grid / n_ph, so
+// that the heavy first items of the phases (each class is sorted by degree,
+// descending) land on different wavefronts.
+std::vector<uint32_t> rotate_ranges(const std::vector<uint32_t> &prefix, int32_t n_ph, int32_t nw,
+                                    int32_t waves_per_block);
+
 // For each phase and workgroup (waves_per_block consecutive wavefronts), the
 // 64-bit spin words written by that workgroup alone: [lo, hi), or [0, 0).
-// Words shared with a neighbouring workgroup's items are left out.
-std::vector<uint32_t> own_words(const HostLayout &L, const std::vector<uint32_t> &wave_ptr, int32_t n_ph,
+// Words shared with a neighbouring workgroup's items are left out.  ranges
+// as from rotate_ranges.
+std::vector<uint32_t> own_words(const HostLayout &L, const std::vector<uint32_t> &ranges, int32_t n_ph,
                                 int32_t grid, int32_t waves_per_block, int Lbits);
 
 // Largest number of chunks per lane, sum of ceil(len4 / g) over its items,
 // that one wavefront's items of all phases hold; *max_items (if not NULL):
-// the most items one wavefront has in all phases.
-uint64_t max_wave_chunks(const HostLayout &L, const std::vector<uint32_t> &wave_ptr, int32_t n_ph, int32_t nw,
+// the most items one wavefront has in all phases.  ranges as from
+// rotate_ranges.
+uint64_t max_wave_chunks(const HostLayout &L, const std::vector<uint32_t> &ranges, int32_t n_ph, int32_t nw,
                          uint64_t *max_items);
 
 // Verifies that every item addresses only memory inside the layout (index

@@ -37,7 +37,7 @@ SCHED_EXPLICIT = 1
 
 EXPORTED = ["isingCreate", "isingRandomizeSpins", "isingSetSpins", "isingAnneal", "isingCut",
             "isingGetSpins", "isingUpdateBest", "isingGetBest", "isingGetColoring", "isingTotalWeight",
-            "isingSetField", "isingGetInfo",
+            "isingSetField", "isingSetFlipScale", "isingGetInfo",
             "isingDestroy", "isingLastError", "isingAnnealNoAlloc"]
 
 NOALLOC_MAX_SWEEPS = 65536  # ISING_NOALLOC_MAX_SWEEPS (include/ising_noalloc.h)
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "isingGetColoring": [P, P, P],
         "isingTotalWeight": [P, P],
         "isingSetField": [P, P, P],
+        "isingSetFlipScale": [P, P, P],
         "isingGetInfo": [P, ctypes.POINTER(Info)],
         "isingDestroy": [P],
     }
@@ -187,6 +188,10 @@ def isingTotalWeight(h, W):
 
 def isingSetField(h, field, stream=None):
     return _lib.isingSetField(h, _ptr(field), _stream(stream))
+
+
+def isingSetFlipScale(h, scale, stream=None):
+    return _lib.isingSetFlipScale(h, _ptr(scale), _stream(stream))
 
 
 def isingGetInfo(h, info):
@@ -304,6 +309,12 @@ class Graph:
         if isinstance(h, np.ndarray):
             h = np.ascontiguousarray(h, dtype=np.int32)
         _check(isingSetField(self._h, h, stream), "isingSetField")
+
+    def set_flip_scale(self, m, stream=None):
+        """Per-vertex flip-temperature multipliers (uint8 [n] in [0, 15]; 8 = plain); None removes them."""
+        if isinstance(m, np.ndarray):
+            m = np.ascontiguousarray(m, dtype=np.uint8)
+        _check(isingSetFlipScale(self._h, m, stream), "isingSetFlipScale")
 
     def info(self):
         inf = Info()

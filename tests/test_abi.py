@@ -42,7 +42,8 @@ def test_binding_uses_the_c_names():
 def test_warm_start_header_symbols_are_exported():
     text = open(os.path.join(ROOT, "include", "ising_warm.h")).read()
     names = sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(isingWarm[A-Za-z]+)\s*\(", text, re.M)))
-    assert names == ["isingWarmAggregate", "isingWarmLastError"]
+    assert names == ["isingWarmAggregate", "isingWarmLastError", "isingWarmLayerBackward", "isingWarmLayerForward",
+                     "isingWarmLayerLastError"]
     lib = ctypes.CDLL(_lib_path())
     assert all(hasattr(lib, n) for n in names)
     lib.isingWarmAggregate.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 5 + [ctypes.c_int32, ctypes.c_void_p]

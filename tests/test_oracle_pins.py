@@ -515,3 +515,47 @@ print(O.threads())
     out = subprocess.run([os.sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == threads
+
+
+# --------------------------------------------------------------------------
+# Per-vertex flip temperature (reading R15: vertex v flips in sweep t iff its
+# draw is below min(2^32 - 1, floor(T_t * m_v / 8)), m_v in [0, 15])
+# --------------------------------------------------------------------------
+def test_flip_scale_on_isolated_vertices_follows_the_scaled_threshold(aten_philox):
+    # no edges: only the flips act, so the final spin's sign counts the draws
+    # below each vertex's own threshold, computed here with Python integers
+    n, R, M, seed = 16, 3, 24, 4242
+    g = G.empty(n)
+    T = O.thresholds(1.0, 0.3, M)  # starts at 2^32 - 1, so m > 8 saturates
+    m = np.arange(n, dtype=np.uint8) % 16
+    s0 = G.random_spins(n, R, 8)
+    rows = [[v, t // 4, r, 0, seed & 0xFFFFFFFF, seed >> 32]
+            for r in range(R) for v in range(n) for t in range(M)]
+    words = np.tile(np.arange(M) % 4, R * n)
+    x = aten_philox(rows)[np.arange(R * n * M), words].reshape(R, n, M)
+    thr = np.array([[min(2**32 - 1, (int(T[t]) * int(m[v])) // 8) for t in range(M)] for v in range(n)],
+                   dtype=np.uint64)
+    flips = (x < thr[None, :, :]).sum(axis=2)
+    expect = (s0 * np.where(flips % 2 == 1, -1, 1)).astype(np.int8)
+    col, nc = O.color(g)
+    got = O.anneal(g, O.order(col, nc), s0, T, seed, 0, M, scale=m)
+    assert np.array_equal(got, expect)
+    assert (flips[:, m == 0] == 0).all() and flips[:, m == 15].sum() > 0
+
+
+def test_flip_scale_eight_is_the_plain_anneal_and_zero_is_greedy():
+    g = G.powerlaw_chung_lu(2000, max_deg=150, seed=31)
+    col, nc = O.color(g)
+    o = O.order(col, nc)
+    T = O.thresholds(0.3, 0.0, 40)
+    s0 = O.init_spins(g.n, 2, 17)
+    plain = O.anneal(g, o, s0, T, 17, 0, 40)
+    assert np.array_equal(O.anneal(g, o, s0, T, 17, 0, 40, scale=np.full(g.n, 8, np.uint8)), plain)
+    greedy = O.anneal(g, o, s0, np.zeros(40, np.uint32), 17, 0, 40)
+    assert np.array_equal(O.anneal(g, o, s0, T, 17, 0, 40, scale=np.zeros(g.n, np.uint8)), greedy)
+    # scaling one vertex changes only what its own flips touch: a vertex with
+    # m = 0 next to vertices that keep m = 8 differs from the plain run
+    m = np.full(g.n, 8, np.uint8)
+    m[::7] = 0
+    mixed = O.anneal(g, o, s0, T, 17, 0, 40, scale=m)
+    assert not np.array_equal(mixed, plain)

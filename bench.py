@@ -11,9 +11,8 @@ degree 8, max degree 2000, weights +-1), 2000 sweeps of the linear flip
 schedule 0.1 -> 0, async mode (every sweep synchronised, every neighbour value
 from the current or the previous sweep), largest-first colouring -- the
 configuration whose edge stream is set against the HBM roofline.  The line
-also carries, outside `value`: the run-ahead async option and deterministic
-mode on the same handle, an on-chip figure, and the CPU oracle on one core and
-on every host core.
+also carries, outside `value`: deterministic mode on the same handle, an
+on-chip figure, and the CPU oracle on one core and on every host core.
 
 Prints one JSON line (see the repository's design notes for every field).
 """
@@ -240,7 +239,7 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the step captured in a HIP graph (anneal_ms is then the whole step)")
     ap.add_argument("--no-extra", dest="extra", action="store_false",
-                    help="skip the run-ahead and deterministic context legs")
+                    help="skip the deterministic context leg")
     ap.add_argument("--p-start", type=float, default=0.1, help="initial flip probability of the linear schedule")
     ap.add_argument("--time-to-cut", action="store_true",
                     help="also measure time-to-cut over a ladder of shorter schedules (untimed for 'value')")
@@ -355,9 +354,10 @@ def main():
     mean_anneal_s = float(np.mean(anneal_ms)) / 1e3
     achieved = alg / mean_anneal_s / 1e9
     traffic = measured_traffic(args.traffic, args.workload, args.mode) if M == wl["sweeps"] else None
-    # on-chip: in lock step every workgroup refreshes its LDS copy of each
-    # phase's spin words after the phase, i.e. the whole state once per sweep
-    lds_refresh = info["grid"] * info["spin_bytes"] * groups if info["bins"] == 0 else 0
+    # on-chip: after each phase every workgroup copies the phase's exchange
+    # words (8 bytes per 4-byte spin word) into its LDS copy, i.e. the whole
+    # state once per sweep
+    lds_refresh = info["grid"] * info["spin_bytes"] * 2 * groups if info["bins"] == 0 else 0
     us_sweep = mean_anneal_s / M * 1e6
     out = {
         "metric": "spin-updates/sec",
@@ -396,23 +396,15 @@ def main():
                    "lds_gathers_per_sweep": g.nnz * groups,
                    "lds_gathers_per_s": g.nnz * groups / (mean_anneal_s / M),
                    "note": "gathers are 4-byte LDS reads of neighbour spin words; the refresh copies each "
-                           "phase's spin words from global memory into every workgroup's LDS copy"},
+                           "phase's exchange words (spin word + write count) from global memory into every "
+                           "workgroup's LDS copy"},
         "final_cut_last_step": int(cuts[0]),
         "max_sweep_gap": gr.info()["max_sweep_gap"],
         "sources_sha256": sources_digest(),
         "create_s": create_s,
     }
     if args.extra and args.workload == "powerlaw1m" and mode == I.MODE_ASYNC:
-        # the run-ahead option (not the paper's scheme: a workgroup may run
-        # two sweeps ahead of the slowest one) and deterministic mode, timed
-        # on the same handle for context
-        os.environ["ISING_ASYNC_SLACK"] = "2"
-        try:
-            tot, per = timed_anneals(2, sch, I.MODE_ASYNC, 3000)
-        finally:
-            os.environ.pop("ISING_ASYNC_SLACK", None)
-        out["runahead2_async"] = {"value": g.n * R * M * 2 / (tot / 1e3), "us_per_sweep": float(np.mean(per)) / M * 1e3,
-                                  "final_cut": int(cut.cpu().numpy()[0]), "max_sweep_gap": gr.info()["max_sweep_gap"]}
+        # deterministic mode, timed on the same handle for context
         Md = 200
         tot, per = timed_anneals(2, I.make_schedule(args.p_start, 0.0, Md), I.MODE_DETERMINISTIC, 4000)
         out["deterministic"] = {"sweeps": Md, "us_per_sweep": float(np.mean(per)) / Md * 1e3,

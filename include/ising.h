@@ -94,17 +94,14 @@ typedef enum {
  * ASYNC: the paper's race-tolerant update (Sec. IV-B): every sweep is
  *   synchronised, and inside a sweep a spin reads each neighbour's value
  *   from this sweep or the previous one, never older.  Work is issued in
- *   phases, runs of consecutive colour classes (a class holding at least
- *   half of the vertices stays on its own), separated by device-wide
- *   barriers: a neighbour in an earlier phase is read at this sweep's
- *   value, one in a later phase at the previous sweep's, and one in the
- *   same phase at either, as the update races with the neighbour's.
- *   Results vary from run to run; they are judged by cut statistics.
- *   The environment variable ISING_ASYNC_SLACK = s (1..8) instead lets a
- *   workgroup run up to s sweeps ahead of the slowest one with no barrier
- *   inside a sweep; neighbour values may then be older than the previous
- *   sweep (isingGetInfo's max_sweep_gap shows how far apart workgroups
- *   were). */
+ *   phases, runs of consecutive colour classes (a run grows while at most
+ *   1 % of the edges lie inside it), and a phase starts only once every
+ *   spin of the previous phase is final: a neighbour in an earlier phase is
+ *   read at this sweep's value, one in a later phase at the previous
+ *   sweep's, and one in the same phase at either, as the update races with
+ *   the neighbour's.  Results vary from run to run; they are judged by cut
+ *   statistics.  isingGetInfo's max_sweep_gap reports how many sweeps apart
+ *   two workgroups were ever seen (0 or 1 by construction). */
 typedef enum { ISING_MODE_DETERMINISTIC = 0, ISING_MODE_ASYNC = 1 } ising_mode_t;
 
 /* Greedy colouring rule.  FIRST_FIT visits vertices in increasing id;
@@ -232,8 +229,8 @@ typedef struct {
   int32_t bins;             /* batched mode: workgroups per replica group, each owning whole
                                connected components (0: one cooperative launch) */
   int32_t max_sweep_gap;    /* cooperative launch: the largest number of sweeps by which
-                               workgroups were apart at a grid barrier over the handle's life
-                               (0 or 1 in lock step); reading it synchronises the device */
+                               workgroups were seen apart at a phase end over the handle's
+                               life (0 or 1); reading it synchronises the device */
   int32_t resident_edges;   /* cooperative launch: bit m set if mode m (0 deterministic, 1 async)
                                reads the +-1 edge entries from HBM once per call and keeps them
                                in registers (3 bytes each) for all its sweeps */

@@ -30,7 +30,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(out_dir, exist_ok=True)
     common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    objs = []
+    objs, procs = [], []
+    # the sources compile in parallel (kernels.hip dominates)
     for src in SOURCES:
         obj = os.path.join(out_dir, src + ".o")
         cmd = [hipcc(), *common, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -38,8 +39,11 @@ def build(verbose: bool = False) -> str:
                     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    for cmd, p in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:

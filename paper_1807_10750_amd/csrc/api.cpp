@@ -102,7 +102,10 @@ struct ising_graph_s {
   int32_t *d_vid = nullptr;
   Item *d_items = nullptr;
   uint32_t *d_wave_ptr[2] = {nullptr, nullptr};  // per mode: [phases][nw][2] item ranges
-  uint32_t *d_own_w64[2] = {nullptr, nullptr};   // per mode: [phases][grid][2]
+  // exchange words of a launch with the LDS copy (kernels.hip): [n_words]
+  // words and the bits each word's items write per sweep
+  unsigned long long *d_xch = nullptr;
+  uint8_t *d_cover = nullptr;
   uint32_t *d_flips = nullptr;                   // 3 flip planes per replica group
   // batched mode: one workgroup per (bin of whole components, replica group)
   bool batch = false;
@@ -159,7 +162,7 @@ ising_status_t dev_alloc(T **p, size_t bytes, const char *what) {
 
 void free_all(ising_graph_s *g) {
   void *bufs[] = {g->d_entries, g->d_wts4, g->d_vid, g->d_items, g->d_wave_ptr[0], g->d_wave_ptr[1],
-                  g->d_cls_w64[0], g->d_cls_w64[1], g->d_own_w64[0], g->d_own_w64[1], g->d_flips,
+                  g->d_cls_w64[0], g->d_cls_w64[1], g->d_xch, g->d_cover, g->d_flips,
                   g->d_bin_wave_ptr, g->d_bin_words,
                   g->d_spins, g->d_thr, g->d_bar, g->d_cut, g->d_stage, g->d_bias,
                   g->d_best_cut, g->d_best_spins, g->d_best_mask, g->d_cutvals, g->d_scale};
@@ -375,7 +378,6 @@ ising_status_t internal_anneal(ising_graph_t g, uint64_t seed, ising_mode_t mode
   a.items = g->d_items;
   const int m = mode == ISING_MODE_ASYNC ? 1 : 0;
   a.wave_ptr = g->d_wave_ptr[m];
-  a.own_w64 = g->d_own_w64[m];
   a.cls_w64 = g->d_cls_w64[m];
   a.thr = thr;
   a.thr_base = thr_base;
@@ -387,8 +389,6 @@ ising_status_t internal_anneal(ising_graph_t g, uint64_t seed, ising_mode_t mode
   a.seed_lo = (uint32_t)seed;
   a.seed_hi = (uint32_t)(seed >> 32);
   a.spin_limit = (uint32_t)std::max<int64_t>(1000, env_int("ISING_BARRIER_POLLS", 20000000));
-  // async run-ahead window (sweeps); 0, the default, keeps the workgroups in lock step
-  a.async_slack = (uint32_t)std::min<int64_t>(8, std::max<int64_t>(0, env_int("ISING_ASYNC_SLACK", 0)));
   if (g->batch) {
     a.spins = g->d_spins;
     a.flips = g->d_flips;
@@ -402,12 +402,18 @@ ising_status_t internal_anneal(ising_graph_t g, uint64_t seed, ising_mode_t mode
     HIP_TRY(launch_batch(g, a, g->batch_waves, st), "batched anneal launch");
     return ISING_OK;
   }
-  // keep the barrier epochs below 2^31 within one launch
-  const bool runahead = a.async_mode && a.async_slack > 0;
-  // (the lock-step top counter reaches epochs x groups, at most 8 groups)
-  const int64_t barriers_per_sweep = g->grid > 1 ? (runahead ? 1 : 8 * std::max(1, a.n_phases)) : 0;
+  // Counts within one launch.  Exchange words (launch with the LDS copy; one
+  // workgroup uses them too, without waiting on them): a word's count
+  // reaches 32 times the sweeps, kept below 2^26.  Arrival counters:
+  // epochs (phases, at least two per sweep) times at most 1024 workgroups,
+  // kept below 2^31; without the LDS copy the barrier's top counter reaches
+  // epochs times at most 8 groups.
+  const bool xch = g->use_lds;
   int64_t chunk = sweep_end - sweep_begin;
-  if (barriers_per_sweep > 0) chunk = std::max<int64_t>(1, ((int64_t)1 << 30) / barriers_per_sweep);
+  if (xch) chunk = std::min<int64_t>(chunk, (int64_t)1 << 20);
+  if (g->grid > 1)
+    chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, ((int64_t)1 << 30) / (1024 * std::max(2, a.n_phases))));
+  a.xch = g->d_xch;
   for (int grp = 0; grp < g->n_groups; ++grp) {
     a.spins = g->d_spins + (size_t)grp * g->n_words;
     a.flips = g->d_flips + (size_t)grp * 3 * g->n_words;
@@ -417,10 +423,12 @@ ising_status_t internal_anneal(ising_graph_t g, uint64_t seed, ising_mode_t mode
       a.t_begin = t0;
       a.t_end = std::min(sweep_end, t0 + chunk);
       HIP_TRY(launch_fill_u32(g->d_bar + kBarTop, 1, 0u, st), "barrier reset");
-      HIP_TRY(launch_fill_u32(g->d_bar + kBarGroup, kBarFlags + (uint32_t)g->grid - kBarGroup, 0u, st),
-              "barrier reset");
+      HIP_TRY(launch_fill_u32(g->d_bar + kBarGroup, 16 * 8, 0u, st), "barrier reset");
+      if (xch) HIP_TRY(launch_fill_u32(g->d_bar + kBarArrive, kArriveCounters * kArriveStride, 0u, st), "arrival reset");
+      if (xch) HIP_TRY(launch_xch_init(a.spins, g->d_cover, g->d_xch, g->n_words, st), "exchange words");
       HIP_TRY(launch_anneal(g->L, g->lay.enc, g->use_lds, g->res_edges[m], a, g->grid, g->lds_bytes, st),
               "anneal launch");
+      if (xch) HIP_TRY(launch_xch_fini(g->d_xch, a.spins, g->n_words, st), "exchange words");
     }
   }
   return ISING_OK;
@@ -574,7 +582,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   // phase tables: deterministic = one colour class per phase; async merges
   // consecutive classes while the edges inside a phase stay within a budget
   // (ISING_ASYNC_MERGE, in units of 0.1 % of the edges)
-  std::vector<uint32_t> wave_ptr[2], cls_w64[2], own_w64[2];
+  std::vector<uint32_t> wave_ptr[2], cls_w64[2];
   const double merge_budget = 0.001 * (double)std::max<int64_t>(0, env_int("ISING_ASYNC_MERGE", kAsyncMergeBudget));
   for (int m = 0; m < 2; ++m) {
     std::vector<int32_t> pc;
@@ -589,7 +597,6 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
     }
     g->n_phases[m] = (int32_t)pc.size() - 1;
     wave_ptr[m] = rotate_ranges(partition_waves(lay, pc, g->nw, true), g->n_phases[m], g->nw, waves_per_block);
-    own_w64[m] = own_words(lay, wave_ptr[m], g->n_phases[m], g->grid, waves_per_block, L);
     // register-resident entries when every wavefront's items fit them
     if (!g->batch && g->use_lds && L == 1 && lay.enc == kEncPm1 && lay.n_slots <= kResMaxSlots &&
         env_int("ISING_RESIDENT_EDGES", 1) != 0) {
@@ -649,16 +656,23 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
     if ((r = dev_alloc(&g->d_wave_ptr[m], sizeof(uint32_t) * wave_ptr[m].size(), "wave table")) != ISING_OK) return bail(r);
     if ((r = upload(g->d_wave_ptr[m], wave_ptr[m].data(), sizeof(uint32_t) * wave_ptr[m].size(), "wave upload")) != ISING_OK)
       return bail(r);
-    if ((r = dev_alloc(&g->d_own_w64[m], sizeof(uint32_t) * own_w64[m].size(), "ownership table")) != ISING_OK)
-      return bail(r);
-    if ((r = upload(g->d_own_w64[m], own_w64[m].data(), sizeof(uint32_t) * own_w64[m].size(), "ownership upload")) !=
-        ISING_OK)
-      return bail(r);
     if ((r = dev_alloc(&g->d_cls_w64[m], sizeof(uint32_t) * cls_w64[m].size(), "class table")) != ISING_OK) return bail(r);
     if ((r = upload(g->d_cls_w64[m], cls_w64[m].data(), sizeof(uint32_t) * cls_w64[m].size(), "class upload")) != ISING_OK)
       return bail(r);
   }
   if ((r = dev_alloc(&g->d_spins, sizeof(uint32_t) * (size_t)g->n_words * g->n_groups, "spins")) != ISING_OK) return bail(r);
+  if (g->use_lds && !g->batch) {
+    // exchange words: one replica group at a time (groups run one after another)
+    std::vector<uint8_t> cover;
+    try {
+      cover = word_cover(lay, L, g->n_words);
+    } catch (const std::bad_alloc &) {
+      return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed for the word cover"));
+    }
+    if ((r = dev_alloc(&g->d_xch, sizeof(unsigned long long) * g->n_words, "exchange words")) != ISING_OK) return bail(r);
+    if ((r = dev_alloc(&g->d_cover, cover.size(), "word cover")) != ISING_OK) return bail(r);
+    if ((r = upload(g->d_cover, cover.data(), cover.size(), "word cover upload")) != ISING_OK) return bail(r);
+  }
   if ((r = dev_alloc(&g->d_flips, sizeof(uint32_t) * 3 * (size_t)g->n_words * g->n_groups, "flip planes")) != ISING_OK)
     return bail(r);
   if (g->batch) {

@@ -43,6 +43,11 @@ hipError_t launch_check_spins(const int8_t *src, int64_t count, uint32_t *flag, 
 hipError_t launch_cut_finalize(const unsigned long long *sums, int32_t R, int64_t *cut, int64_t *energy,
                                hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t count, uint32_t value, hipStream_t s);
+// Exchange words around a launch with the LDS copy: spin words in with zero
+// counts and their covers before, spin words out after.
+hipError_t launch_xch_init(const uint32_t *spins, const uint8_t *cover, unsigned long long *xch, uint32_t n_words,
+                           hipStream_t s);
+hipError_t launch_xch_fini(const unsigned long long *xch, uint32_t *spins, uint32_t n_words, hipStream_t s);
 // Best-of-run update from the cut sums of every replica (see k_best_select).
 hipError_t launch_best(const unsigned long long *sums, int32_t R, int32_t L, int32_t reset, int64_t *best,
                        int64_t *cut_out, uint32_t *masks, const uint32_t *spins, uint32_t *best_spins,

@@ -9,23 +9,45 @@
 // block at counter {v, t div 4, r, 0}, key = seed, so one block serves four
 // consecutive sweeps.
 //
-// Work is issued in phases, each a run of colour classes, with a grid
-// barrier after every phase.  In deterministic mode a phase is one class,
-// which makes the result equal to a sequential sweep in (colour, id) order.
-// In async mode a phase merges small classes, so neighbours inside a phase
-// update concurrently and read each other's value from this sweep or the
-// previous one, as in the paper's unsynchronised update; with a run-ahead
-// window there is no barrier inside a sweep at all.  Every wavefront keeps
-// the loads of its next item in flight while it computes the current one.
+// Work is issued in phases, each a run of colour classes.  In
+// deterministic mode a phase is one class, which makes the result equal to a
+// sequential sweep in (colour, id) order.  In async mode a phase merges
+// small classes, so neighbours inside a phase update concurrently and read
+// each other's value from this sweep or the previous one, as in the paper's
+// unsynchronised update, while every sweep stays synchronised.  Every
+// wavefront keeps the loads of its next item in flight while it computes
+// the current one.
 //
 // Spin state is an L-bit mask per slot (replica bits) packed in uint32
 // words.  When it fits, each workgroup keeps a copy of the whole state in
 // LDS and neighbour gathers are LDS reads; the edge stream is read once per
 // sweep with 16-byte coalesced loads, or, with +-1 weights and one replica
 // bit per slot, once per call into registers that every wavefront keeps for
-// all its sweeps (its items never change within a call).  All global spin
-// traffic uses agent-scope atomics, which are coherent across the XCDs' L2
-// caches.
+// all its sweeps (its items never change within a call).
+//
+// Phase ends of a multi-workgroup launch with the LDS copy synchronise
+// through the data itself.  During the call the spin words live in
+// exchange words: word i in bits [31:0] of a 64-bit word, in bits [57:32]
+// the number of its bits written so far in the call, and in bits [63:58]
+// cover[i], the bits of the word that items write each sweep (32 unless a
+// colour class ends inside the word).  A writer adds (new bits - old bits)
+// + (bits it covers << 32) in one 64-bit atomic add (its bits are disjoint
+// from every other writer's, so the difference replaces exactly them and
+// never carries into the count); every covered bit is written once per
+// sweep, so after sweep k of the call the count of word i is cover[i] * k
+// (an item that writes a word whole stores it outright with that count).
+// A phase ends with an arrival of every workgroup, a no-return add on one
+// of 32 counters, issued without waiting for its writes to land; once all
+// have arrived a workgroup copies the phase's words into
+// LDS, and the counts show which words still have a write in flight (those
+// are read again).  No store-completion wait, no returned atomic and no
+// second counter level sit on that path.  Arrivals also keep every
+// workgroup within one phase of the others, so no word is overwritten
+// before every workgroup has copied it.  Without the LDS copy, phases end
+// with a counter-tree grid barrier and neighbours are read from global
+// memory.
+// All cross-workgroup spin traffic uses agent-scope atomics, which are
+// coherent across the XCDs' L2 caches.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -235,113 +257,175 @@ __device__ __forceinline__ T wave_sum(T x) {
 }
 
 // ---------------------------------------------------------------------------
-// Grid barriers of a cooperative launch.  Epochs count from 1.
-//
-// Lock step (deterministic mode, async mode without run-ahead): no
-// workgroup arrives at epoch k + 1 before epoch k is complete, so counters
-// suffice.  Workgroups arrive on one of eight group counters (blockIdx mod
-// 8, one per XCD), the last arrival of a group bumps the top counter, and
-// epoch k is complete when the top counter reaches k times the number of
-// groups.
-//
-// Run-ahead (async_slack >= 1): a workgroup may arrive several epochs ahead
-// of others, so arrivals are per workgroup: workgroup b stores the epoch it
-// reached in its own flag word, and a wait for epoch k has thread t poll
-// flag t until it reads at least k, so an epoch completes only when every
-// workgroup has arrived at it.
-//
-// Spin state crosses workgroups only through agent-scope atomics, so with
-// the LDS copy a barrier needs no cache maintenance, only completed stores
-// (s_waitcnt); without the LDS copy neighbour reads are plain loads and
-// agent fences are used.  A poll limit bounds every wait; hitting it raises
-// the error flag and every workgroup leaves the kernel.
+// Grid barrier of a cooperative launch without the LDS copy.  Epochs count
+// from 1; no workgroup arrives at epoch k + 1 before epoch k is complete, so
+// counters suffice.  Workgroups arrive on one of eight group counters
+// (blockIdx mod 8, one per XCD), the last arrival of a group bumps the top
+// counter, and epoch k is complete when the top counter reaches k times the
+// number of groups.  Neighbour reads are then plain loads, so arrivals are
+// agent release fences and waits agent acquire fences.  A poll limit bounds
+// every wait; hitting it raises the error flag and every workgroup leaves
+// the kernel.
 // ---------------------------------------------------------------------------
-// LDS words of the barrier: the verdict of a wait, the lowest and highest
-// flag it saw, and the largest sweep gap this workgroup has seen.
+// LDS words of the phase ends: the verdict of a wait (cleared on failure
+// only) and the largest sweep gap this workgroup has seen.
 struct BarLds {
-  uint32_t ok, lo, hi, gap;
+  uint32_t ok, gap;
 };
 
-__device__ __forceinline__ void bar_arrive(const AnnealArgs &a, bool fenced, uint32_t epoch, bool flags) {
-  if (fenced)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  else
-    __builtin_amdgcn_s_waitcnt(0);
+__device__ __forceinline__ void bar_arrive(const AnnealArgs &a) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (flags) {
-      st_coherent(a.bar + kBarFlags + blockIdx.x, epoch);
-    } else {
-      const uint32_t grp = blockIdx.x & 7u;
-      const uint32_t gsize = (gridDim.x - grp + 7u) / 8u;
-      const uint32_t old = __hip_atomic_fetch_add(a.bar + kBarGroup + 16 * grp, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-      if ((old + 1u) % gsize == 0u)
-        __hip_atomic_fetch_add(a.bar + kBarTop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    const uint32_t grp = blockIdx.x & 7u;
+    const uint32_t gsize = (gridDim.x - grp + 7u) / 8u;
+    const uint32_t old = __hip_atomic_fetch_add(a.bar + kBarGroup + 16 * grp, 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if ((old + 1u) % gsize == 0u)
+      __hip_atomic_fetch_add(a.bar + kBarTop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// Waits until every workgroup has arrived at barrier epoch `target`, and
-// records in s.gap how many sweeps (of epochs_per_sweep epochs) apart the
-// workgroups were when this one left the wait: with flags, from the highest
-// and lowest flag read; with counters, from how far the top counter had
-// gone past the target.
-__device__ __forceinline__ bool bar_wait(const AnnealArgs &a, uint32_t target, bool fenced, BarLds &s,
-                                         uint32_t epochs_per_sweep, bool flags) {
-  uint32_t *bar = a.bar;
-  const uint32_t limit = a.spin_limit;
-  if (flags) {
-    if (threadIdx.x == 0) {
-      s.ok = 1u;
-      s.lo = 0xFFFFFFFFu;
-      s.hi = 0u;
-    }
-    __syncthreads();
-    if (threadIdx.x < gridDim.x) {
-      uint32_t polls = 0, f;
-      while ((f = ld_coherent(bar + kBarFlags + threadIdx.x)) < target) {
-        if (++polls > limit ||
-            ((polls & 63u) == 0u && __hip_atomic_load(bar + kBarErr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-          __hip_atomic_store(bar + kBarErr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          s.ok = 0u;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      atomicMin(&s.lo, f);
-      atomicMax(&s.hi, f);
-    }
-    if (fenced && threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0 && s.hi > s.lo) {
-      const uint32_t gap = (s.hi - s.lo + epochs_per_sweep - 1u) / epochs_per_sweep;
-      s.gap = gap > s.gap ? gap : s.gap;
-    }
-    return __builtin_amdgcn_readfirstlane(s.ok) != 0u;  // wave-uniform, so loops stay scalar
+// Polls-limit test shared by every wait: true when this wait must give up
+// (its own limit, or another workgroup raised the error flag).
+__device__ __forceinline__ bool give_up(const AnnealArgs &a, uint32_t &polls) {
+  if (++polls > a.spin_limit ||
+      ((polls & 63u) == 0u && __hip_atomic_load(a.bar + kBarErr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+    __hip_atomic_store(a.bar + kBarErr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
   }
+  return false;
+}
+
+// Waits until every workgroup has arrived at barrier epoch `target`.
+__device__ __forceinline__ bool bar_wait(const AnnealArgs &a, uint32_t target, BarLds &s) {
   const uint32_t n_grp = gridDim.x < 8u ? gridDim.x : 8u;
   if (threadIdx.x == 0) {
-    uint32_t ok = 1, polls = 0, top;
-    while ((top = __hip_atomic_load(bar + kBarTop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target * n_grp) {
-      if (__hip_atomic_load(bar + kBarErr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++polls > limit) {
-        __hip_atomic_store(bar + kBarErr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
+    uint32_t polls = 0;
+    while (__hip_atomic_load(a.bar + kBarTop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target * n_grp) {
+      if (give_up(a, polls)) {
+        s.ok = 0u;
         break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    if (ok && top > target * n_grp) {
-      // some group already completed a later epoch
-      const uint32_t ahead = (top - target * n_grp + n_grp - 1u) / n_grp;
-      const uint32_t gap = (ahead + epochs_per_sweep - 1u) / epochs_per_sweep;
-      s.gap = gap > s.gap ? gap : s.gap;
-    }
-    if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    s.ok = ok;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   return __builtin_amdgcn_readfirstlane(s.ok) != 0u;  // wave-uniform, so loops stay scalar
+}
+
+// ---------------------------------------------------------------------------
+// Exchange words (multi-workgroup launch with the LDS copy; see the header)
+// ---------------------------------------------------------------------------
+// Publishes a writer's part of exchange word w: its bits go from ov to nv
+// and it covers `cover` bits of the word.  (The writer's own LDS update of
+// the word needs no ordering against it: a workgroup copies a phase's
+// words into LDS only after a workgroup barrier that follows every item of
+// the phase, and the barrier waits for all LDS writes.)
+__device__ __forceinline__ void xch_add(const AnnealArgs &a, uint32_t w, uint32_t nv, uint32_t ov, uint32_t cover) {
+  const unsigned long long add =
+      (unsigned long long)((long long)nv - (long long)ov) + ((unsigned long long)cover << 32);
+  __hip_atomic_fetch_add(a.xch + w, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A word that one item writes whole (every sweep, so cover 32): stored
+// outright with the count it has after sweep t of the call.
+__device__ __forceinline__ void xch_store(const AnnealArgs &a, uint32_t w, uint32_t nv, uint32_t t) {
+  const uint32_t k = t - (uint32_t)a.t_begin + 1u;
+  st_coherent64(a.xch + w, (unsigned long long)nv | ((unsigned long long)(32u * k) << 32) | (32ull << 58));
+}
+
+// Arrival at exchange epoch `epoch` (counted from 1 over the launch) and
+// the wait for every workgroup's arrival: once all its wavefronts are past
+// the phase, workgroup b adds one to counter b mod 32 (no return), and
+// epoch e is complete when counter j reaches e times the number of
+// workgroups that use it; lane j of the first wavefront polls counter j.
+// Adds to one address serialise at the memory side (one counter for the
+// whole grid measured twice as slow as eight), hence many counters, each
+// on its own page.  ahead_gap: the sweep gap to record if another
+// workgroup is seen past this epoch already.
+__device__ __forceinline__ bool xch_arrive_wait(const AnnealArgs &a, uint32_t epoch, uint32_t ahead_gap, BarLds &s) {
+  const uint32_t tid = threadIdx.x;
+  constexpr uint32_t C = kArriveCounters;
+  __syncthreads();
+  if (tid == 0)
+    __hip_atomic_fetch_add(a.bar + kBarArrive + kArriveStride * (blockIdx.x % C), 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  if (tid < C && tid < gridDim.x) {
+    const uint32_t want = epoch * ((gridDim.x - tid + C - 1u) / C);
+    uint32_t *cnt = a.bar + kBarArrive + kArriveStride * tid;
+    uint32_t polls = 0, c;
+    while ((c = ld_coherent(cnt)) < want) {
+      if (give_up(a, polls)) {
+        s.ok = 0u;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (c > want && ahead_gap > 0u) atomicMax(&s.gap, ahead_gap);
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(s.ok) != 0u;
+}
+
+// End of phase ph of sweep k (1-based within the call): every workgroup
+// arrives, then copies the phase's spin words into LDS; a word whose count
+// shows a write still in flight is read again until complete.  With one
+// phase per sweep a second arrival follows the copy, so no workgroup writes
+// the phase's words of the next sweep before every copy is done (with more
+// phases the next arrival implies it).  Each thread keeps XB words in
+// flight.  Returns false when a wait gave up.
+template <uint32_t XB>
+__device__ __forceinline__ bool xch_phase_end(const AnnealArgs &a, uint32_t *lds, int32_t ph, bool last_phase,
+                                              uint32_t k, uint32_t &epoch, BarLds &s) {
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  if (!xch_arrive_wait(a, ++epoch, last_phase ? 1u : 0u, s)) return false;
+  // complete: the count (bits [57:32]) equals the cover (bits [63:58]) times k
+  auto complete = [k](unsigned long long x) {
+    const uint32_t hi = (uint32_t)(x >> 32);
+    return (hi & 0x3FFFFFFu) == (hi >> 26) * k;
+  };
+  bool ok = true;
+  const uint32_t b = 2u * ro(a.cls_w64, ph), e = 2u * ro(a.cls_w64, ph + 1);
+  for (uint32_t i0 = b + tid; ok && i0 < e; i0 += XB * nt) {
+    unsigned long long v[XB];
+#pragma unroll
+    for (uint32_t j = 0; j < XB; ++j)
+      if (i0 + j * nt < e) v[j] = ld_coherent64(a.xch + i0 + j * nt);
+    uint32_t pend = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < XB; ++j) {
+      const uint32_t i = i0 + j * nt;
+      if (i < e) {
+        if (complete(v[j]))
+          lds[i] = (uint32_t)v[j];
+        else
+          pend |= 1u << j;
+      }
+    }
+    uint32_t polls = 0;
+    while (pend != 0u) {
+      if (give_up(a, polls)) {
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+#pragma unroll
+      for (uint32_t j = 0; j < XB; ++j)
+        if ((pend >> j) & 1u) v[j] = ld_coherent64(a.xch + i0 + j * nt);
+#pragma unroll
+      for (uint32_t j = 0; j < XB; ++j)
+        if (((pend >> j) & 1u) && complete(v[j])) {
+          lds[i0 + j * nt] = (uint32_t)v[j];
+          pend &= ~(1u << j);
+        }
+    }
+  }
+  if (!ok) s.ok = 0u;
+  if (a.n_phases == 1 && !xch_arrive_wait(a, ++epoch, 0u, s)) return false;
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(s.ok) != 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -363,8 +447,11 @@ struct Fetched {
 // share of the sliced-ELL chunks (chunks g, g + G, ...).
 // plane: flip plane to read for this item's sweep (-1 when the sweep draws).
 // RC > 0: the chunks are register-resident; only the row data is loaded.
-template <int L, int ENC, bool FIELD, int RC = 0>
-__device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, int lane, Fetched<L, ENC> &f, int plane) {
+// XCH: the spin words live in the exchange words during the call; this
+// workgroup's LDS copy always holds its own rows' current bits.
+template <int L, int ENC, bool FIELD, int RC = 0, bool XCH = false>
+__device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, int lane, Fetched<L, ENC> &f, int plane,
+                                      const uint32_t *lds = nullptr) {
   const Item it = uni(it_in);
   constexpr int KM = Fetched<L, ENC>::KM;
   const uint32_t G = it.g, gs = (uint32_t)__builtin_ctz(G), ks = 6u - gs;
@@ -378,7 +465,7 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
   f.bias = FIELD && RC == 0 ? a.bias[slot] : 0;
   // Only this item (so this workgroup) writes its row's spin and flip bits,
   // and only those bits are used: workgroup-scope loads are enough.
-  f.ownw = RC > 0 ? 0u : ld_workgroup(a.spins + ((slot * L) >> 5));
+  f.ownw = RC > 0 ? 0u : (XCH ? lds[(slot * L) >> 5] : ld_workgroup(a.spins + ((slot * L) >> 5)));
   f.flipw = RC == 0 && plane >= 0 ? ld_workgroup(a.flips + (size_t)plane * a.n_words + ((slot * L) >> 5)) : 0u;
   // the item's block starts at a wave-uniform address; offsets inside it fit 32 bits
   const uint4 *blk = a.entries + it.base4;
@@ -405,14 +492,16 @@ __device__ __forceinline__ void fetch(const AnnealArgs &a, const Item &it_in, in
 // register, j the next item's index.
 struct ResState {
   uint32_t cr, j, own, flip;
-  uint32_t pw, px;  // spin word with a pending XOR and the XOR (wave-uniform)
+  uint32_t pw;              // exchange word with a pending addition (wave-uniform)
+  unsigned long long pv;    // the pending addition, 0 when none
 };
 
-// Applies a wavefront's pending XOR to the global spin state.
+// Applies a wavefront's pending addition to its exchange word.
 __device__ __forceinline__ void flush_pending(const AnnealArgs &a, ResState &rs, int lane) {
-  if (rs.px != 0u && lane == 0)
-    __hip_atomic_fetch_xor(a.spins + rs.pw, rs.px, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  rs.px = 0u;
+  if (rs.pv != 0ull && lane == 0) {
+    __hip_atomic_fetch_add(a.xch + rs.pw, rs.pv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  rs.pv = 0ull;
 }
 
 // LDS word of the anneal's mirror array past the spin state that holds 0:
@@ -455,11 +544,15 @@ __device__ __forceinline__ void load_resident(const AnnealArgs &a, const Item &i
 // woff: the spin word that lds[0] holds (0 when LDS mirrors the whole state).
 // RC > 0: the item's chunks sit in rw from chunk rs->cr on, its spin and
 // flip bits in rs (load_resident); rs moves on to the next item.
-template <int L, int ENC, bool USE_LDS, bool FIELD, int RC = 0>
+// XCH: new spin words go to the LDS copy and the exchange words (xch_add)
+// instead of the global spin words.
+template <int L, int ENC, bool USE_LDS, bool FIELD, int RC = 0, bool XCH = false>
 __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, int lane, const Fetched<L, ENC> &f,
                                         uint32_t *lds, uint32_t t, bool draws, uint32_t woff = 0,
                                         const uint32_t *rw = nullptr, ResState *rs = nullptr) {
   static_assert(RC == 0 || L == 1, "resident state holds one replica bit per slot");
+  static_assert(RC == 0 || XCH, "resident state publishes through the exchange words");
+  static_assert(!XCH || USE_LDS, "the exchange words serve the LDS copy");
   const Item it = uni(it_in);
   constexpr int KM = Fetched<L, ENC>::KM;
   constexpr bool kPm1 = ENC == kEncPm1;
@@ -561,13 +654,17 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   }
   const bool rep = gl == 0u;
   if (K * L >= 32u) {
-    // the item owns whole words: plain coherent stores
+    // the item owns whole words
     if (L == 1 && G == 1u) {
       const unsigned long long b = __ballot(nm & 1u);
-      // with resident state the word's current value is known: an
-      // unchanged word is not stored again (nothing else writes it)
-      const bool store = RC == 0 || __ballot(nm != own) != 0ull;
-      if (lane == 0 && store) {
+      if constexpr (XCH) {
+        if (lane < 2) {
+          const uint32_t w = (it.id >> 5) + (uint32_t)lane;
+          const uint32_t nv = (uint32_t)(b >> (32 * lane));
+          lds[w] = nv;
+          xch_store(a, w, nv, t);
+        }
+      } else if (lane == 0) {
         st_coherent64(reinterpret_cast<unsigned long long *>(a.spins) + (it.id >> 6), b);
         if (USE_LDS) reinterpret_cast<unsigned long long *>(lds)[(it.id >> 6) - (woff >> 1)] = b;
       }
@@ -586,8 +683,13 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
       uint32_t val = rep ? nm << sh : 0u;
       for (uint32_t off = G; off < G * P; off <<= 1) val |= __shfl_xor(val, (int)off);
       if (rep && (r % P) == 0u) {
-        st_coherent(a.spins + (bit0 >> 5), val);
-        if (USE_LDS) lds[(bit0 >> 5) - woff] = val;
+        if constexpr (XCH) {
+          lds[bit0 >> 5] = val;
+          xch_store(a, bit0 >> 5, val, t);
+        } else {
+          st_coherent(a.spins + (bit0 >> 5), val);
+          if (USE_LDS) lds[(bit0 >> 5) - woff] = val;
+        }
       }
       if (RC == 0 && draws) {
         const uint32_t first = t & 3u;
@@ -601,19 +703,29 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
       }
     }
   } else {
-    // all K rows share one word with other items: exact XOR of the changes
+    // all K rows share one word with other items: the exact change of this
+    // item's bits (XOR for the LDS copy, a difference for the exchange word)
     uint32_t chg = rep ? (own ^ nm) << sh : 0u;
-    for (uint32_t off = G; off < 64u; off <<= 1) chg |= __shfl_xor(chg, (int)off);
+    uint32_t nv = XCH && rep ? nm << sh : 0u;
+    for (uint32_t off = G; off < 64u; off <<= 1) {
+      chg |= __shfl_xor(chg, (int)off);
+      if (XCH) nv |= __shfl_xor(nv, (int)off);
+    }
     if constexpr (RC > 0) {
       // consecutive items of a wavefront often share the word: their
-      // changes are combined into one global XOR (the LDS copy at once)
-      const uint32_t wd = uni(bit0 >> 5), cu = uni(chg);
+      // additions are combined into one (the LDS copy changes at once)
+      const uint32_t wd = uni(bit0 >> 5), cu = uni(chg), nu = uni(nv);
       if (lane == 0 && cu != 0u) atomicXor(lds + wd, cu);
       if (wd != rs->pw) {
         flush_pending(a, *rs, lane);
         rs->pw = wd;
       }
-      rs->px ^= cu;
+      rs->pv += (unsigned long long)((long long)nu - (long long)(nu ^ cu)) + ((unsigned long long)(K * L) << 32);
+    } else if constexpr (XCH) {
+      if (lane == 0) {
+        if (chg != 0u) atomicXor(lds + (bit0 >> 5), chg);
+        xch_add(a, bit0 >> 5, nv, nv ^ chg, K * L);
+      }
     } else if (lane == 0 && chg != 0u) {
       __hip_atomic_fetch_xor(a.spins + (bit0 >> 5), chg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (USE_LDS) atomicXor(lds + ((bit0 >> 5) - woff), chg);
@@ -676,15 +788,14 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int gw = blockIdx.x * kWaves + wib;
   const bool multi = gridDim.x > 1;
-  const bool fenced = !USE_LDS;
-  // deterministic mode, and async mode without run-ahead, end every phase
-  // with a grid barrier
-  const bool lockstep = !a.async_mode || a.async_slack == 0u;
   // Pipeline shape that fits the registers: two items in flight (three
   // buffers), one item in flight unrolled, or one item in flight rolled.
   constexpr bool kDeep = ENC == kEncPm1 && L <= 4 && RC == 0;
   constexpr bool kUnrolled = L <= 4 && RC == 0;
-  if (threadIdx.x == 0) s_bar.gap = 0u;
+  if (threadIdx.x == 0) {
+    s_bar.ok = 1u;
+    s_bar.gap = 0u;
+  }
   if (USE_LDS) {
     if (RC > 0 && threadIdx.x == 0) mirror[kZeroWord] = 0u;
     restage(a, lds, 0, a.n_words / 2, threadIdx.x, blockDim.x);
@@ -696,7 +807,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   // resident chunks of this wavefront's items, phase by phase in item order
   // (the order the sweeps visit them); cr is the next chunk's register
   uint32_t rw[RC > 0 ? 3 * RC : 3] = {};
-  ResState rs{0u, 0u, 0u, 0u, 0u, 0u};
+  ResState rs{0u, 0u, 0u, 0u, 0u, 0ull};
   if constexpr (RC > 0) {
     for (int32_t ph = 0; ph < a.n_phases; ++ph) {
       const uint32_t b = ro(a.wave_ptr, range_at(ph)), e = ro(a.wave_ptr, range_at(ph) + 1);
@@ -712,13 +823,19 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   Item ita;
   if (ib < ie) {
     ita = ro_item(a.items, ib);
-    fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, plane_of(a.t_begin));
+    fetch<L, ENC, FIELD, RC, USE_LDS>(a, ita, lane, fa, plane_of(a.t_begin), lds);
   }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
     const int plane = plane_of(t);
     rs.cr = 0;
     rs.j = 0;
     for (int32_t ph = 0; ph < a.n_phases; ++ph) {
+      // vmcnt(0) before the items, where nothing is in flight any more (the
+      // phase end copied, and waited for, every word): without it the
+      // compiler, unsure whether a load of the phase end is still in flight
+      // at the item loop's head, waits there on every item for every
+      // earlier memory operation, the previous item's exchange store included.
+      if constexpr (RC > 0) __builtin_amdgcn_s_waitcnt(0x0F70);
       // Items of this phase.  On entry fa holds the loads of item ib.  The
       // loop is unrolled by the pipeline depth so the buffers change roles
       // without register copies (a copy would wait for its loads).
@@ -729,30 +846,30 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         Item itb, itc, pre;
         if (ib + 1 < ie) {
           itb = ro_item(a.items, ib + 1);
-          fetch<L, ENC, FIELD, RC>(a, itb, lane, fb, plane);
+          fetch<L, ENC, FIELD, RC, USE_LDS>(a, itb, lane, fb, plane, lds);
         }
         if (ib + 2 < ie) pre = ro_item(a.items, ib + 2);
         for (uint32_t i = ib; i < ie; i += 3) {
           if (i + 2 < ie) {
             itc = pre;
-            fetch<L, ENC, FIELD, RC>(a, itc, lane, fc, plane);
+            fetch<L, ENC, FIELD, RC, USE_LDS>(a, itc, lane, fc, plane, lds);
             if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
           if (i + 1 >= ie) break;
           if (i + 3 < ie) {
             ita = pre;
-            fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, plane);
+            fetch<L, ENC, FIELD, RC, USE_LDS>(a, ita, lane, fa, plane, lds);
             if (i + 4 < ie) pre = ro_item(a.items, i + 4);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
           if (i + 2 >= ie) break;
           if (i + 4 < ie) {
             itb = pre;
-            fetch<L, ENC, FIELD, RC>(a, itb, lane, fb, plane);
+            fetch<L, ENC, FIELD, RC, USE_LDS>(a, itb, lane, fb, plane, lds);
             if (i + 5 < ie) pre = ro_item(a.items, i + 5);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, itc, lane, fc, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, itc, lane, fc, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
         }
       } else if (kUnrolled) {
         // one item ahead: fa, fb in rotation
@@ -761,17 +878,17 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         for (uint32_t i = ib; i < ie; i += 2) {
           if (i + 1 < ie) {
             itb = pre;
-            fetch<L, ENC, FIELD, RC>(a, itb, lane, fb, plane);
+            fetch<L, ENC, FIELD, RC, USE_LDS>(a, itb, lane, fb, plane, lds);
             if (i + 2 < ie) pre = ro_item(a.items, i + 2);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
           if (i + 1 >= ie) break;
           if (i + 2 < ie) {
             ita = pre;
-            fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, plane);
+            fetch<L, ENC, FIELD, RC, USE_LDS>(a, ita, lane, fa, plane, lds);
             if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
         }
       } else {
         // one item ahead, rolled: the copy waits for the next item's loads
@@ -780,9 +897,9 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           Item itb;
           if (more) {
             itb = ro_item(a.items, i + 1);
-            fetch<L, ENC, FIELD, RC>(a, itb, lane, fb, plane);
+            fetch<L, ENC, FIELD, RC, USE_LDS>(a, itb, lane, fb, plane, lds);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
           if (more) {
             ita = itb;
             fa = fb;
@@ -799,71 +916,40 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
       ib = ro(a.wave_ptr, range_at(nph));
       ie = ro(a.wave_ptr, range_at(nph) + 1);
       if (done) ie = ib;
-      if (multi && lockstep) {
-        // A grid barrier ends every phase; after it every workgroup
-        // refreshes its LDS copy of the words the phase wrote.  In
-        // deterministic mode a phase is one colour class, so the sweep
-        // equals the sequential one in (colour, id) order.  In async mode a
-        // phase is a run of classes: a neighbour of an earlier phase is read
-        // at its value of this sweep, a neighbour of a later phase at its
-        // value of the previous sweep, and a neighbour of the same phase at
-        // either (the race of the paper's update; the LDS copy holds its own
+      if (multi && USE_LDS) {
+        // Every sweep stays synchronised and no value older than the
+        // previous sweep is read: after phase ph every workgroup copies the
+        // phase's words once complete (xch_phase_end).  In deterministic
+        // mode a phase is one colour class, so the sweep equals the
+        // sequential one in (colour, id) order.  In async mode a phase is a
+        // run of classes: a neighbour of an earlier phase is read at its
+        // value of this sweep, a neighbour of a later phase at its value of
+        // the previous sweep, and a neighbour of the same phase at either
+        // (the race of the paper's update; the LDS copy holds its own
         // workgroup's updates at once and the others' from the previous
-        // barrier on).  No value older than the previous sweep is read.
-        bar_arrive(a, fenced, epoch + 1u, false);
+        // sweep's copy on).
         if (ib < ie) {
           ita = ro_item(a.items, ib);
-          fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, next_plane);
+          fetch<L, ENC, FIELD, RC, USE_LDS>(a, ita, lane, fa, next_plane, lds);
+        }
+        // (the register-resident variant has fewer registers to spare)
+        if (!done &&
+            !xch_phase_end<(RC > 0 ? 4u : 8u)>(a, lds, ph, last_phase, (uint32_t)(t - a.t_begin + 1), epoch, s_bar))
+          return;
+      } else if (multi) {
+        // without the LDS copy: a grid barrier ends every phase
+        bar_arrive(a);
+        if (ib < ie) {
+          ita = ro_item(a.items, ib);
+          fetch<L, ENC, FIELD, RC, USE_LDS>(a, ita, lane, fa, next_plane, lds);
         }
         ++epoch;
-        if (!bar_wait(a, epoch, fenced, s_bar, (uint32_t)a.n_phases, false)) return;
-        if (USE_LDS) {
-          restage(a, lds, ro(a.cls_w64, ph), ro(a.cls_w64, ph + 1), threadIdx.x, blockDim.x);
-          __syncthreads();
-        }
-      } else if (multi) {
-        // async with run-ahead (async_slack >= 1): no wait inside a sweep.
-        // Each wave refreshes its share of the phase's spin words from the
-        // global state right after its own items of the phase, skipping the
-        // words only this workgroup writes (its LDS copy of those is the
-        // freshest).  A word shared with another workgroup may then lag in
-        // LDS, and a workgroup may run up to async_slack sweeps ahead of
-        // the slowest one, so a neighbour's value can be older than the
-        // previous sweep.
-        if (ib < ie) {
-          ita = ro_item(a.items, ib);
-          fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, next_plane);
-        }
-        // At the end of a sweep the workgroup arrives first (its stores of
-        // the sweep are complete) and refreshes after: the refresh then
-        // overlaps the other workgroups' work instead of delaying them.
-        // The last sweep of the call needs no refresh.
-        const bool sweep_end = last_phase && !done;
-        if (sweep_end) bar_arrive(a, fenced, epoch + 1u, true);
-        if (USE_LDS && !done) {
-          const size_t oi = ((size_t)ph * gridDim.x + blockIdx.x) * 2;
-          const uint32_t o0 = ro(a.own_w64, oi), o1 = ro(a.own_w64, oi + 1);
-          const uint32_t b = ro(a.cls_w64, ph), e = ro(a.cls_w64, ph + 1);
-          const uint32_t ol = o0 > b ? o0 : b, oh = o1 < e ? o1 : e;
-          const uint32_t first = (uint32_t)(wib * kWave + lane);
-          if (ol < oh) {
-            restage(a, lds, b, ol, first, blockDim.x);
-            restage(a, lds, oh, e, first, blockDim.x);
-          } else {
-            restage(a, lds, b, e, first, blockDim.x);
-          }
-        }
-        if (sweep_end) {
-          // after its sweep k a workgroup waits until every workgroup has
-          // finished sweep k - async_slack
-          ++epoch;
-          if (epoch > a.async_slack && !bar_wait(a, epoch - a.async_slack, fenced, s_bar, 1u, true)) return;
-        }
+        if (!bar_wait(a, epoch, s_bar)) return;
       } else {
         // one workgroup: its LDS copy is current
         if (ib < ie) {
           ita = ro_item(a.items, ib);
-          fetch<L, ENC, FIELD, RC>(a, ita, lane, fa, next_plane);
+          fetch<L, ENC, FIELD, RC, USE_LDS>(a, ita, lane, fa, next_plane, lds);
         }
         if (!a.async_mode || last_phase) {
           if (!USE_LDS) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1032,6 +1118,19 @@ __global__ void k_best_merge(const uint32_t *spins, uint32_t *best, const uint32
     for (int32_t k = 0; k < 32; k += L) pat |= m << k;  // the replica bits of every slot in the word
     best[w] = (best[w] & ~pat) | (spins[w] & pat);
   }
+}
+
+// Exchange words of one anneal launch: the spin words with zero counts and
+// their covers.
+__global__ void k_xch_init(const uint32_t *spins, const uint8_t *cover, unsigned long long *xch, uint32_t n_words) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += gridDim.x * blockDim.x)
+    xch[i] = (unsigned long long)spins[i] | ((unsigned long long)cover[i] << 58);
+}
+
+// The spin words back from the exchange words after the launch.
+__global__ void k_xch_fini(const unsigned long long *xch, uint32_t *spins, uint32_t n_words) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += gridDim.x * blockDim.x)
+    spins[i] = (uint32_t)xch[i];
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t count, uint32_t value) {
@@ -1314,6 +1413,19 @@ hipError_t launch_cut_finalize(const unsigned long long *sums, int32_t R, int64_
                                hipStream_t s) {
   const int grid = (int)std::min<int32_t>(64, R / 256 + 1);
   hipLaunchKernelGGL(k_cut_finalize, dim3(grid), dim3(256), 0, s, sums, R, cut, energy);
+  return hipGetLastError();
+}
+
+hipError_t launch_xch_init(const uint32_t *spins, const uint8_t *cover, unsigned long long *xch, uint32_t n_words,
+                           hipStream_t s) {
+  const int grid = (int)std::min<uint32_t>(1024u, n_words / 256 + 1);
+  hipLaunchKernelGGL(k_xch_init, dim3(grid), dim3(256), 0, s, spins, cover, xch, n_words);
+  return hipGetLastError();
+}
+
+hipError_t launch_xch_fini(const unsigned long long *xch, uint32_t *spins, uint32_t n_words, hipStream_t s) {
+  const int grid = (int)std::min<uint32_t>(1024u, n_words / 256 + 1);
+  hipLaunchKernelGGL(k_xch_fini, dim3(grid), dim3(256), 0, s, xch, spins, n_words);
   return hipGetLastError();
 }
 

@@ -56,14 +56,18 @@ struct Item {
 };
 
 // Words of the per-handle flag buffer.
-constexpr int kBarTop = 0;       // lock-step barrier: epochs completed x groups
-constexpr int kBarErr = 1;       // set when a barrier poll limit is hit
+constexpr int kBarTop = 0;       // grid barrier: epochs completed x groups
+constexpr int kBarErr = 1;       // set when a poll limit is hit
 constexpr int kBarCheck = 2;     // spin-value check result
-constexpr int kBarGap = 3;       // largest sweep gap between workgroups seen at a barrier
-constexpr int kBarGroup = 16;    // lock-step barrier: group counter k at kBarGroup + 16 * k, k < 8
-constexpr int kBarFlags = 256;   // run-ahead barrier: the epoch workgroup b reached, at kBarFlags + b
+constexpr int kBarGap = 3;       // largest sweep gap between workgroups seen at a phase end
+constexpr int kBarGroup = 16;    // grid barrier: group counter k at kBarGroup + 16 * k, k < 8
+// phase-end arrival counters of the exchange words: counter j (workgroups
+// b mod 32 = j) at kBarArrive + j * kArriveStride, each in its own page
+constexpr int kArriveCounters = 32;
+constexpr int kArriveStride = 1088;  // words: 4 KiB + 256 B, so counters fall in different channels
+constexpr int kBarArrive = 1024;
+constexpr int kBarWords = kBarArrive + kArriveCounters * kArriveStride;
 constexpr int kBarMaxGrid = 1024;  // at most one polling thread per workgroup of the grid
-constexpr int kBarWords = kBarFlags + kBarMaxGrid;
 
 // Arguments of the anneal kernel (passed by value).
 struct AnnealArgs {
@@ -80,7 +84,10 @@ struct AnnealArgs {
   const uint32_t *cls_w64;   // [n_phases + 1] class boundaries in 64-bit words of the spin state
   uint32_t *spins;           // this replica group's spin words
   uint32_t *flips;           // 3 planes of n_words: flip bits of sweeps 4b+1..4b+3
-  const uint32_t *own_w64;   // [n_phases][grid][2] 64-bit spin words only this workgroup writes
+  // exchange words of a launch with an LDS mirror (see kernels.hip): spin word i in bits
+  // [31:0] of xch[i], the count of its bits written so far in this call in bits [57:32], the
+  // bits of it that items write each sweep in bits [63:58]
+  unsigned long long *xch;
   const uint32_t *thr;       // thresholds: sweep t's at thr[t - thr_base]
   int64_t thr_base;
   uint32_t *bar;             // barrier words (see kBar*), error flag
@@ -92,9 +99,7 @@ struct AnnealArgs {
   uint32_t seed_lo, seed_hi;
   uint32_t r0;               // replica index of bit 0
   uint32_t r_count;          // replicas of the group in use (<= L)
-  uint32_t spin_limit;       // barrier polls before giving up (error flag)
-  uint32_t async_slack;      // async: sweeps a workgroup may run ahead of the slowest one
-                             // (0: lock step, a grid barrier after every phase)
+  uint32_t spin_limit;       // polls of a wait before giving up (error flag)
   // batched launch only
   const uint32_t *bin_words; // [n_bins + 1] first 32-bit spin word of each bin
   int32_t n_bins;            // bins (workgroups per replica group)

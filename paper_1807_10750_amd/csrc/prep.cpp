@@ -414,27 +414,17 @@ uint64_t max_wave_chunks(const HostLayout &L, const std::vector<uint32_t> &range
   return most;
 }
 
-std::vector<uint32_t> own_words(const HostLayout &L, const std::vector<uint32_t> &ranges, int32_t n_ph,
-                                int32_t grid, int32_t waves_per_block, int Lbits) {
-  std::vector<uint32_t> out((size_t)n_ph * grid * 2, 0);
-  const int32_t nw = grid * waves_per_block;
-  for (int32_t p = 0; p < n_ph; ++p)
-    for (int32_t g = 0; g < grid; ++g) {
-      // the workgroup's waves hold consecutive item ranges (rotation moves whole workgroups)
-      const uint32_t i0 = ranges[((size_t)p * nw + (size_t)g * waves_per_block) * 2];
-      const uint32_t i1 = ranges[((size_t)p * nw + (size_t)(g + 1) * waves_per_block - 1) * 2 + 1];
-      uint32_t *o = &out[((size_t)p * grid + g) * 2];
-      if (i0 >= i1) continue;
-      const Item &f = L.items[i0], &l = L.items[i1 - 1];
-      const uint64_t bit_lo = (uint64_t)f.id * Lbits;
-      const uint64_t bit_hi = ((uint64_t)l.id + 64 / l.g) * Lbits;
-      const uint64_t lo = (bit_lo + 63) / 64, hi = bit_hi / 64;
-      if (lo < hi) {
-        o[0] = (uint32_t)lo;
-        o[1] = (uint32_t)hi;
-      }
+std::vector<uint8_t> word_cover(const HostLayout &L, int Lbits, uint32_t n_words) {
+  std::vector<uint8_t> cover(n_words, 0);
+  for (const Item &it : L.items) {
+    const uint64_t b0 = (uint64_t)it.id * (uint64_t)Lbits, b1 = b0 + (uint64_t)(64 / it.g) * (uint64_t)Lbits;
+    for (uint64_t bit = b0; bit < b1;) {
+      const uint64_t w = bit >> 5, end = std::min<uint64_t>(b1, (w + 1) << 5);
+      if (w < n_words) cover[w] = (uint8_t)(cover[w] + (end - bit));
+      bit = end;
     }
-  return out;
+  }
+  return cover;
 }
 
 bool check_layout(const HostLayout &L, const HostCSR &g, std::string *msg) {

@@ -93,12 +93,11 @@ std::vector<uint32_t> partition_waves(const HostLayout &L, const std::vector<int
 std::vector<uint32_t> rotate_ranges(const std::vector<uint32_t> &prefix, int32_t n_ph, int32_t nw,
                                     int32_t waves_per_block);
 
-// For each phase and workgroup (waves_per_block consecutive wavefronts), the
-// 64-bit spin words written by that workgroup alone: [lo, hi), or [0, 0).
-// Words shared with a neighbouring workgroup's items are left out.  ranges
-// as from rotate_ranges.
-std::vector<uint32_t> own_words(const HostLayout &L, const std::vector<uint32_t> &ranges, int32_t n_ph,
-                                int32_t grid, int32_t waves_per_block, int Lbits);
+// Bits of each 32-bit spin word that items write every sweep: item i
+// covers the Lbits bits of each of its K = 64 / g slots, so a word gets 32
+// unless the class ends inside it (slots past the class's last item are
+// never written).  [n_words] entries, each at most 32.
+std::vector<uint8_t> word_cover(const HostLayout &L, int Lbits, uint32_t n_words);
 
 // Largest number of chunks per lane, sum of ceil(len4 / g) over its items,
 // that one wavefront's items of all phases hold; *max_items (if not NULL):

@@ -15,9 +15,6 @@ Every lock-step run must also report a sweep gap of at most one between
 workgroups (isingGetInfo), the bound that keeps every neighbour value within
 the previous sweep.
 """
-import contextlib
-import os
-
 import numpy as np
 import pytest
 
@@ -34,21 +31,6 @@ def I():
         pytest.skip("no GPU")
     from paper_1807_10750_amd import ising
     return ising
-
-
-@contextlib.contextmanager
-def env(**kw):
-    old = {k: os.environ.get(k) for k in kw}
-    try:
-        for k, v in kw.items():
-            os.environ[k] = str(v)
-        yield
-    finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
 
 
 def oracle_cuts(g, M, seeds, jacobi=False):
@@ -110,20 +92,3 @@ def test_async_cut_statistics_match_oracle(I, name, make, M):
         assert info["grid"] > 1, "async mode must run multi-workgroup here"
     assert info["max_sweep_gap"] <= 1
     assert abs(a.mean() - o.mean()) <= tol
-
-
-@pytest.mark.parametrize("slack", [1, 3])
-def test_runahead_option(I, slack):
-    # the run-ahead window is an option, not the paper's scheme: workgroups
-    # stay within the window (the flag barrier waits for every workgroup),
-    # and the cuts are valid; their statistics are printed, not banded
-    g = G.powerlaw_chung_lu(100_000, seed=6)
-    M = 200
-    with env(ISING_ASYNC_SLACK=slack):
-        a, info = gpu_async_cuts(I, g, M, 100, 16)
-    o = oracle_cuts(g, M, range(200, 208))
-    print(f"[run-ahead {slack}] async mean {a.mean():.1f} | oracle mean {o.mean():.1f} "
-          f"| gap={info['max_sweep_gap']}", flush=True)
-    assert info["grid"] > 1
-    assert info["max_sweep_gap"] <= slack + 1
-    assert a.mean() > 0.9 * o.mean()

@@ -113,6 +113,99 @@ def time_to_cut(I, torch, gr, g, offsets, M, R, mode, ladder, seed=7):
             "median_member_ms": first(0.5), "all_members_ms": first(1.0), "ladder": rows}
 
 
+def member_cuts_device(torch, spins, eu, ev, ew, member, n_members):
+    """member_cuts on the device: spins int8 [R, n] (torch, device)."""
+    cut_e = (spins[:, eu] != spins[:, ev]).to(torch.int64) * ew[None, :]
+    out = torch.zeros((spins.shape[0], n_members), dtype=torch.int64, device=spins.device)
+    out.scatter_add_(1, member[None, :].expand(spins.shape[0], -1), cut_e)
+    return out.cpu().numpy()
+
+
+def batch_leg(I, torch, sweeps=1000, replays=3, ladder=(62, 125, 250, 500)):
+    """The batched workload (4096 ER graphs x 8 replicas): the whole step
+    (randomize, anneal, cut) captured once per schedule in a HIP graph and
+    replayed; its throughput, and time-to-cut per member graph from the
+    replays of a ladder of shorter schedules."""
+    g, offsets = make_graph("batch4096")
+    R = WORKLOADS["batch4096"]["replicas"]
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    gr = I.Graph.from_csr(g, replicas=R)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    info = gr.info()
+    u, v, w = g.edges()
+    eu = torch.from_numpy(u.astype(np.int64)).to(dev)
+    ev = torch.from_numpy(v.astype(np.int64)).to(dev)
+    ew = torch.from_numpy(w.astype(np.int64)).to(dev)
+    member = torch.from_numpy((np.searchsorted(offsets, u, side="right") - 1).astype(np.int64)).to(dev)
+    cut = torch.zeros(R, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    rows, target = [], None
+    for Mp in sorted(set(ladder) | {sweeps}, reverse=True):
+        sch = I.make_schedule(0.1, 0.0, Mp)
+        # one eager step first: the library stages a schedule's thresholds on
+        # its first use, which a capture must not contain
+        gr.randomize(7)
+        gr.anneal(sch, 7, I.MODE_ASYNC)
+        gr.cut_device(cut)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            gr.randomize(7)
+            gr.anneal(sch, 7, I.MODE_ASYNC)
+            gr.cut_device(cut)
+        graph.replay()  # warm replay
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(replays):
+            graph.replay()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / replays
+        spins = torch.from_numpy(gr.spins()).to(dev)
+        mc = member_cuts_device(torch, spins, eu, ev, ew, member, len(offsets) - 1)
+        if target is None:
+            target = np.median(mc, axis=0)
+        reached = float(np.mean(mc.max(axis=0) >= target))
+        rows.append({"sweeps": Mp, "step_ms": ms, "reached": reached})
+        print(f"# batch4096 graph replay: {Mp} sweeps {ms:.2f} ms/step, reached {reached:.3f}", file=sys.stderr,
+              flush=True)
+        del graph
+    gr.close()
+    rows.sort(key=lambda r: r["sweeps"])
+    full = next(r for r in rows if r["sweeps"] == sweeps)
+    first = lambda frac: next((r["step_ms"] for r in rows if r["reached"] >= frac), None)
+    return {"workload": WORKLOADS["batch4096"]["desc"], "mode": "async", "n": g.n, "nnz": g.nnz,
+            "members": int(len(offsets) - 1), "replicas": R, "create_s": create_s,
+            "block": info["block"], "bins": info["bins"],
+            "value": g.n * R * sweeps / (full["step_ms"] / 1e3), "unit": "spin-updates/s",
+            "step_ms": full["step_ms"], "us_per_sweep": full["step_ms"] / sweeps * 1e3,
+            "time_to_cut": {"definition": "per member graph: GPU ms of a captured step (random start, linear "
+                                          "p 0.1 -> 0, cut) with the shortest schedule whose best-of-8 cut "
+                                          "reaches the member's median final cut of the 1000-sweep schedule",
+                            "median_member_ms": first(0.5), "all_members_ms": first(1.0), "ladder": rows}}
+
+
+def warm_leg(torch):
+    """Time-to-cut of the learned warm start on a held-out 20k-vertex random
+    3-regular +-1 graph (16 replicas): warm spins and flip multipliers +
+    short schedule, against plain random-start annealing and two controls."""
+    from paper_1807_10750_amd import graphs as G
+    from paper_1807_10750_amd import warmstart as WS
+    params = WS.load()
+    g = G.random_regular(20000, 3, "pm1", 900001)  # training never draws this seed
+    r = WS.time_to_cut(params, g)
+    keep = ("target_median_plain_cut", "plain_sweeps", "replicas", "p_warm", "plain_ms", "warm_ms",
+            "warm_spins_only_ms", "cold_random_ms")
+    out = {k: r[k] for k in keep}
+    out["workload"] = "held-out random 3-regular n=20000, w +-1, deterministic mode"
+    out["warm_ladder"] = [{k: x[k] for k in ("sweeps", "infer_ms", "total_ms", "best_cut", "reached")}
+                          for x in r["warm_ladder"]]
+    return out
+
+
 def sources_digest():
     """SHA-256 over the sources that decide what the anneal kernel reads and writes."""
     import hashlib
@@ -239,7 +332,7 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the step captured in a HIP graph (anneal_ms is then the whole step)")
     ap.add_argument("--no-extra", dest="extra", action="store_false",
-                    help="skip the deterministic context leg")
+                    help="skip the context legs (deterministic mode, the batched workload, the warm start)")
     ap.add_argument("--p-start", type=float, default=0.1, help="initial flip probability of the linear schedule")
     ap.add_argument("--time-to-cut", action="store_true",
                     help="also measure time-to-cut over a ladder of shorter schedules (untimed for 'value')")
@@ -409,6 +502,11 @@ def main():
         tot, per = timed_anneals(2, I.make_schedule(args.p_start, 0.0, Md), I.MODE_DETERMINISTIC, 4000)
         out["deterministic"] = {"sweeps": Md, "us_per_sweep": float(np.mean(per)) / Md * 1e3,
                                 "value": g.n * R * Md * 2 / (tot / 1e3), "coloring": args.coloring}
+    if args.extra and args.workload == "powerlaw1m":
+        print("# batch4096 leg ...", file=sys.stderr, flush=True)
+        out["batch4096"] = batch_leg(I, torch)
+        print("# warm-start leg ...", file=sys.stderr, flush=True)
+        out["warm_start"] = warm_leg(torch)
     if args.time_to_cut:
         out["time_to_cut"] = time_to_cut(I, torch, gr, g, offsets, M, R, mode, [M // 16, M // 8, M // 4, M // 2])
     if args.cpu_budget > 0:

@@ -1139,7 +1139,12 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t count, uint32_t value) {
 
 // ---------------------------------------------------------------------------
 // Cut and energy (Eq. 4 and Eq. 5 with J = -w) of one replica bit, summed
-// over directed entries (each undirected edge twice).
+// over directed entries (each undirected edge twice).  With +-1 weights a
+// wavefront counts with ballots: for each entry position of a chunk, the
+// lanes whose entry is a cut edge of weight +1 and those of weight -1 are
+// two 64-bit masks, and popc(first) - popc(second) is the wavefront's
+// contribution to the cut; the energy follows from the same masks and the
+// signs of all real entries.
 // ---------------------------------------------------------------------------
 template <int L, int ENC>
 __global__ __launch_bounds__(256) void k_cut(CutArgs a) {
@@ -1156,7 +1161,35 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs a) {
     // external field energy -h s, once per row (padding rows carry 0)
     if (a.bias != nullptr && gl == 0u) f_sum += (long long)(a.bias[slot] >> 1) * (own ? 1 : -1);
     int32_t e_part = 0, c_part = 0;
-    for (uint32_t q = gl; q < it.len4; q += G) {
+    if constexpr (ENC == kEncPm1) {
+      // every lane runs the same number of chunk steps (the item's longest
+      // share), so the ballots see the whole wavefront; lanes past their
+      // share contribute nothing
+      const uint32_t steps = (it.len4 + G - 1u) / G;
+      for (uint32_t st = 0; st < steps; ++st) {
+        const uint32_t q = gl + st * G;
+        const bool live = q < it.len4;
+        uint4 x4 = make_uint4(slot, slot, slot, slot);  // padding: names the row itself
+        if (live) x4 = a.entries[(size_t)it.base4 + (size_t)q * K + r];
+        const uint32_t xs[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t nb = xs[k] & ~kSignBit;
+          const bool real = nb != slot;
+          const bool neg = (xs[k] & kSignBit) != 0u;
+          const bool cut = real && ((mask_of<L>(a.spins, real ? nb : slot) >> a.bit) & 1u) != own;
+          // cut edges of weight +1 and -1; real entries of weight +1 and -1
+          const long long cp = __popcll(__ballot(cut && !neg)), cn = __popcll(__ballot(cut && neg));
+          const long long rp = __popcll(__ballot(real && !neg)), rn = __popcll(__ballot(real && neg));
+          if (lane == 0) {
+            c_sum += cp - cn;
+            // sum of w s s = sum of w over real entries - 2 (sum of w over cut entries)
+            e_sum += (rp - rn) - 2 * (cp - cn);
+          }
+        }
+      }
+    }
+    for (uint32_t q = gl; ENC != kEncPm1 && q < it.len4; q += G) {
       const size_t c = (size_t)it.base4 + (size_t)q * K + r;
       const uint4 x4 = a.entries[c];
       const uint32_t wv = ENC == kEncWide ? a.wts4[c] : 0u;

@@ -148,10 +148,17 @@ struct ising_graph_s {
 
 namespace {
 
+// Failure injection for tests of the error paths: with ISING_FAULT_INJECT =
+// k >= 1, the k-th device allocation of each isingCreate call fails as if
+// the device were out of memory (counted per thread from the call's start).
+thread_local int64_t g_alloc_count = 0;
+thread_local int64_t g_alloc_fail_at = 0;
+
 template <typename T>
 ising_status_t dev_alloc(T **p, size_t bytes, const char *what) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
+  if (g_alloc_fail_at > 0 && ++g_alloc_count == g_alloc_fail_at) return hip_fail(hipErrorOutOfMemory, what);
   hipError_t e = hipMalloc(reinterpret_cast<void **>(p), bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -471,9 +478,12 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
 
   ising_graph_s *g = new (std::nothrow) ising_graph_s();
   if (g == nullptr) return fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed");
+  g_alloc_count = 0;
+  g_alloc_fail_at = std::max<int64_t>(0, env_int("ISING_FAULT_INJECT", 0));
   auto bail = [&](ising_status_t s) {
     free_all(g);
     delete g;
+    g_alloc_fail_at = 0;
     return s;
   };
   g->n = n;
@@ -725,6 +735,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   // the edge stream is on the device now; keep only what later calls need
   std::vector<uint32_t>().swap(lay.entries);
   std::vector<int8_t>().swap(lay.wts);
+  g_alloc_fail_at = 0;
   *out = g;
   return ISING_OK;
 }

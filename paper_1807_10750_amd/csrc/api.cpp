@@ -8,6 +8,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <sys/stat.h>
 #include <tuple>
 #include <vector>
 
@@ -283,7 +284,7 @@ hipError_t launch_batch(const ising_graph_s *g, AnnealArgs a, int waves, hipStre
 // table and returns the index of the fastest.  The spins and flip planes
 // are clobbered; the caller resets them.
 ising_status_t time_batch_shapes(ising_graph_s *g, const std::vector<std::vector<uint32_t>> &tables,
-                                 const int *waves, hipStream_t st, int *best) {
+                                 const int *waves, hipStream_t st, int *best, float *best_ms_out) {
   constexpr int kSweeps = 8;
   uint32_t *d_tab = nullptr, *d_thr = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -339,8 +340,69 @@ ising_status_t time_batch_shapes(ising_graph_s *g, const std::vector<std::vector
   if (e1) (void)hipEventDestroy(e1);
   if (d_tab) (void)hipFree(d_tab);
   if (d_thr) (void)hipFree(d_thr);
+  if (best_ms_out != nullptr) *best_ms_out = best_ms;
   return r;
 }
+
+// Options of one handle build.  bin_target: vertices per bin of the batched
+// layout (0: ISING_BIN_VERTICES, default 4096); waves: wavefronts per
+// workgroup of the batched launch (0: ISING_BATCH_WAVES, else timed);
+// tuned_ms (out, may be NULL): the 8-sweep time of the timed choice, or -1.
+struct CreateOpts {
+  int64_t bin_target = 0;
+  int waves = 0;
+  float *tuned_ms = nullptr;
+};
+
+// The persisted choices of the batched launch shape: one line per input
+// shape, "n nnz replicas coloring bin_target waves", in the file named by
+// ISING_TUNE_CACHE (empty: none), else $HOME/.cache/ising_tune.txt.
+std::string tune_cache_path() {
+  const char *e = std::getenv("ISING_TUNE_CACHE");
+  if (e != nullptr) return std::string(e);
+  const char *home = std::getenv("HOME");
+  if (home == nullptr || *home == 0) return std::string();
+  return std::string(home) + "/.cache/ising_tune.txt";
+}
+
+bool tune_cache_get(int64_t n, int64_t nnz, int32_t R, int coloring, int64_t *target, int *waves) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return false;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE *f = std::fopen(path.c_str(), "r");
+  if (f == nullptr) return false;
+  long long a, b, t;
+  int c, d, wv;
+  bool found = false;
+  while (std::fscanf(f, "%lld %lld %d %d %lld %d", &a, &b, &c, &d, &t, &wv) == 6)
+    if (a == n && b == nnz && c == R && d == coloring && t > 0 && (wv == 4 || wv == 8 || wv == 16)) {
+      *target = t;
+      *waves = wv;
+      found = true;  // the last matching line wins
+    }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_put(int64_t n, int64_t nnz, int32_t R, int coloring, int64_t target, int waves) {
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE *f = std::fopen(path.c_str(), "a");
+  if (f == nullptr) {
+    // the default directory may not exist yet
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) (void)mkdir(path.substr(0, slash).c_str(), 0755);
+    f = std::fopen(path.c_str(), "a");
+  }
+  if (f == nullptr) return;  // not persisted; the choice still holds for this handle
+  std::fprintf(f, "%lld %lld %d %d %lld %d\n", (long long)n, (long long)nnz, R, coloring, (long long)target, waves);
+  std::fclose(f);
+}
+
+ising_status_t create_impl(ising_graph_t *out, int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                           const int8_t *w, ising_coloring_t coloring, int32_t n_replicas, void *stream,
+                           const CreateOpts &opt);
 
 }  // namespace
 
@@ -441,14 +503,13 @@ ising_status_t internal_anneal(ising_graph_t g, uint64_t seed, ising_mode_t mode
   return ISING_OK;
 }
 
-extern "C" {
+namespace {
 
-const char *isingLastError(void) { return g_last_error.c_str(); }
-
-ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int64_t *row_ptr,
-                           const int32_t *col, const int8_t *w, ising_coloring_t coloring,
-                           int32_t n_replicas, void *stream) {
+ising_status_t create_impl(ising_graph_t *out, int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                           const int8_t *w, ising_coloring_t coloring, int32_t n_replicas, void *stream,
+                           const CreateOpts &opt) {
   g_last_error.clear();
+  if (opt.tuned_ms != nullptr) *opt.tuned_ms = -1.f;
   if (out == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "out is NULL");
   *out = nullptr;
   if (n < 0 || nnz < 0 || n >= (int64_t)0x7FFFFFFF - 64)
@@ -519,7 +580,8 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   if (allow_lds && env_int("ISING_NO_BATCH", 0) == 0 && n > 0) {
     int64_t max_comp = 0;
     try {
-      bin_of = pack_components(csr, std::max<int64_t>(64, env_int("ISING_BIN_VERTICES", 4096)), &n_bins, &max_comp);
+      const int64_t target = opt.bin_target > 0 ? opt.bin_target : env_int("ISING_BIN_VERTICES", 4096);
+      bin_of = pack_components(csr, std::max<int64_t>(64, target), &n_bins, &max_comp);
     } catch (const std::bad_alloc &) {
       return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed while finding components"));
     }
@@ -626,7 +688,7 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   std::vector<uint32_t> bin_words;
   int tune_forced = 0;
   if (g->batch) {
-    tune_forced = (int)env_int("ISING_BATCH_WAVES", 0);
+    tune_forced = opt.waves > 0 ? opt.waves : (int)env_int("ISING_BATCH_WAVES", 0);
     if (tune_forced != 0 && tune_forced != 4 && tune_forced != 8 && tune_forced != 16) tune_forced = 4;
     if (tune_forced == 0 && env_int("ISING_AUTOTUNE", 1) == 0) tune_forced = 4;
     const int32_t nc = g->n_colors;
@@ -714,7 +776,8 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
       if (!cached) {
         hipError_t e = launch_fill_u32(g->d_spins, g->n_words * (uint32_t)g->n_groups, 0xFFFFFFFFu, st);
         if (e != hipSuccess) return bail(hip_fail(e, "initialising spins"));
-        if ((r = time_batch_shapes(g, bin_wave_ptrs, kWaveChoices, st, &pick)) != ISING_OK) return bail(r);
+        if ((r = time_batch_shapes(g, bin_wave_ptrs, kWaveChoices, st, &pick, opt.tuned_ms)) != ISING_OK)
+          return bail(r);
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = pick;
       }
@@ -738,6 +801,73 @@ ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int
   g_alloc_fail_at = 0;
   *out = g;
   return ISING_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *isingLastError(void) { return g_last_error.c_str(); }
+
+// The autotuner of the batched launch: for a graph that takes the batched
+// layout, handles are built with bins of 1024, 2048 and 4096 vertices, each
+// timing 4, 8 and 16 wavefronts per workgroup over 8 sweeps, and the fastest
+// (bins, waves) is kept, persisted per input shape (tune_cache_*), so that
+// later processes build it directly.  ISING_BIN_VERTICES or
+// ISING_BATCH_WAVES force a choice, ISING_AUTOTUNE=0 turns tuning off.
+ising_status_t isingCreate(ising_graph_t *out, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                           const int32_t *col, const int8_t *w, ising_coloring_t coloring,
+                           int32_t n_replicas, void *stream) {
+  const bool tune = env_int("ISING_AUTOTUNE", 1) != 0 && std::getenv("ISING_BIN_VERTICES") == nullptr &&
+                    std::getenv("ISING_BATCH_WAVES") == nullptr;
+  CreateOpts opt;
+  if (!tune) return create_impl(out, n, nnz, row_ptr, col, w, coloring, n_replicas, stream, opt);
+  int64_t target = 0;
+  int waves = 0;
+  if (tune_cache_get(n, nnz, n_replicas, (int)coloring, &target, &waves)) {
+    opt.bin_target = target;
+    opt.waves = waves;
+    return create_impl(out, n, nnz, row_ptr, col, w, coloring, n_replicas, stream, opt);
+  }
+  // the default bins first; a graph that does not take the batched layout ends here
+  float best_ms = -1.f;
+  opt.bin_target = 4096;
+  opt.tuned_ms = &best_ms;
+  ising_status_t r = create_impl(out, n, nnz, row_ptr, col, w, coloring, n_replicas, stream, opt);
+  if (r != ISING_OK || !(*out)->batch || best_ms < 0.f) return r;
+  int64_t best_target = 4096;
+  int best_waves = (*out)->batch_waves;
+  for (int64_t t : {2048, 1024}) {
+    ising_graph_t h = nullptr;
+    float ms = -1.f;
+    CreateOpts o;
+    o.bin_target = t;
+    o.tuned_ms = &ms;
+    if (create_impl(&h, n, nnz, row_ptr, col, w, coloring, n_replicas, stream, o) != ISING_OK) {
+      g_last_error.clear();  // a candidate that cannot be built is skipped
+      continue;
+    }
+    if (h->batch && ms >= 0.f && ms < best_ms) {
+      best_ms = ms;
+      best_target = t;
+      best_waves = h->batch_waves;
+    }
+    DeviceGuard guard(h->device);
+    free_all(h);
+    delete h;
+  }
+  tune_cache_put(n, nnz, n_replicas, (int)coloring, best_target, best_waves);
+  if (best_target == 4096) return ISING_OK;
+  {
+    DeviceGuard guard((*out)->device);
+    free_all(*out);
+    delete *out;
+  }
+  *out = nullptr;
+  opt.bin_target = best_target;
+  opt.waves = best_waves;
+  opt.tuned_ms = nullptr;
+  return create_impl(out, n, nnz, row_ptr, col, w, coloring, n_replicas, stream, opt);
 }
 
 ising_status_t isingDestroy(ising_graph_t g) {

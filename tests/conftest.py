@@ -6,6 +6,10 @@ for p in (ROOT, os.path.join(ROOT, "oracle")):
     if p not in sys.path:
         sys.path.insert(0, p)
 
+# tests do not read or write the user's launch-shape cache file; the test of
+# the cache points it at a file of its own
+os.environ.setdefault("ISING_TUNE_CACHE", "")
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an AMD GPU (MI355X) and the built HIP library")

@@ -62,6 +62,30 @@
  *     ising_status_t; on failure isingLastError() describes the cause.
  *   - Threads: one handle must not be used from two threads at once;
  *     distinct handles are independent.
+ *   - Environment.  No variable changes a result, only how it is computed
+ *     (every launch shape gives the same deterministic result bit for bit),
+ *     except ISING_ASYNC_MERGE, which changes which updates race in async
+ *     mode, and ISING_FAULT_INJECT, which makes isingCreate fail.  Read by
+ *     isingCreate unless noted; unset means the default.
+ *       ISING_AUTOTUNE=0        no launch-shape tuning of batched handles
+ *       ISING_BIN_VERTICES=v    batched bins of at most v vertices (no tuning)
+ *       ISING_BATCH_WAVES=w     w in {4, 8, 16} waves per batched workgroup
+ *                               (no tuning)
+ *       ISING_TUNE_CACHE=path   file of tuned shapes (empty: none; default
+ *                               $HOME/.cache/ising_tune.txt)
+ *       ISING_BATCH_L=l         replicas per workgroup of a one-graph batch
+ *       ISING_NO_BATCH=1        never the batched layout
+ *       ISING_NO_LDS=1          no LDS copy of the spins (global gathers)
+ *       ISING_GRID=g            workgroups of the cooperative launch
+ *       ISING_BIN_SHIFT=k       lanes per row chosen for degree >> k
+ *       ISING_WIDE=1            the separate int8 weight stream for all
+ *                               general weights
+ *       ISING_RESIDENT_EDGES=0  never keep +-1 entries in registers
+ *       ISING_ASYNC_MERGE=b     async phases merge classes while at most
+ *                               b/1000 of the edges lie inside (default 10)
+ *       ISING_BARRIER_POLLS=p   polls before a wait gives up (isingAnneal)
+ *       ISING_FAULT_INJECT=k    the k-th device allocation of each
+ *                               isingCreate fails as out of memory (tests)
  */
 #ifndef ISING_H
 #define ISING_H

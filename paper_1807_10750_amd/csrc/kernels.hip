@@ -209,21 +209,35 @@ __device__ __forceinline__ uint32_t update_mask(const int32_t (&h)[L], uint32_t 
   return (nm ^ flips) & lmask<L>();
 }
 
-// Flip draws of sweep t (reading: word t mod 4 of the Philox block at counter
-// {v, t div 4, r, 0}).  Returns this sweep's flip bits; the bits of the
-// block's later sweeps t' < t_end are returned in later[0..2] (index t' mod 4 - 1).
-// With a per-vertex flip temperature, slot's threshold is min(2^32 - 1,
-// floor(T m / 8)) for its multiplier m.
-template <int L>
-__device__ __forceinline__ uint32_t draw_flips(int32_t v, uint32_t slot, uint32_t t, const AnnealArgs &a,
-                                               uint32_t (&later)[3]) {
+// Flip thresholds of the Philox block that sweep t draws: word k serves sweep
+// 4 (t div 4) + k, zero for the block's sweeps before t or past the call.
+// They are uniform over the grid, so one set of scalar loads serves a sweep.
+struct Thr4 {
+  uint32_t k[4];
+};
+
+__device__ __forceinline__ Thr4 sweep_thresholds(const AnnealArgs &a, uint32_t t) {
   const uint32_t b = t >> 2, w = t & 3u;
-  uint32_t Tk[4];
+  Thr4 th;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const uint32_t tk = 4u * b + (uint32_t)k;
-    Tk[k] = ((uint32_t)k >= w && (int64_t)tk < a.t_end) ? ro(a.thr, (size_t)((int64_t)tk - a.thr_base)) : 0u;
+    th.k[k] = ((uint32_t)k >= w && (int64_t)tk < a.t_end) ? ro(a.thr, (size_t)((int64_t)tk - a.thr_base)) : 0u;
   }
+  return th;
+}
+
+// Flip draws of sweep t (reading: word t mod 4 of the Philox block at counter
+// {v, t div 4, r, 0}) against the sweep's thresholds th.  Returns this
+// sweep's flip bits; the bits of the block's later sweeps t' < t_end are
+// returned in later[0..2] (index t' mod 4 - 1).  With a per-vertex flip
+// temperature, slot's threshold is min(2^32 - 1, floor(T m / 8)) for its
+// multiplier m.
+template <int L>
+__device__ __forceinline__ uint32_t draw_flips(int32_t v, uint32_t slot, uint32_t t, const AnnealArgs &a,
+                                               const Thr4 &th, uint32_t (&later)[3]) {
+  const uint32_t b = t >> 2, w = t & 3u;
+  uint32_t Tk[4] = {th.k[0], th.k[1], th.k[2], th.k[3]};
   if (a.scale != nullptr) {
     const uint64_t m = a.scale[slot];
 #pragma unroll
@@ -548,8 +562,8 @@ __device__ __forceinline__ void load_resident(const AnnealArgs &a, const Item &i
 // instead of the global spin words.
 template <int L, int ENC, bool USE_LDS, bool FIELD, int RC = 0, bool XCH = false>
 __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, int lane, const Fetched<L, ENC> &f,
-                                        uint32_t *lds, uint32_t t, bool draws, uint32_t woff = 0,
-                                        const uint32_t *rw = nullptr, ResState *rs = nullptr) {
+                                        uint32_t *lds, uint32_t t, bool draws, const Thr4 &th, uint32_t woff = 0,
+                                        uint32_t *rw = nullptr, ResState *rs = nullptr) {
   static_assert(RC == 0 || L == 1, "resident state holds one replica bit per slot");
   static_assert(RC == 0 || XCH, "resident state publishes through the exchange words");
   static_assert(!XCH || USE_LDS, "the exchange words serve the LDS copy");
@@ -569,11 +583,11 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
     for (int c = 0; c < RC; ++c) {
       const uint32_t k = (uint32_t)c - cb;
       if (k < nch) {
-        // opaque copies: without them the compiler hoists every entry's
+        // opaque in place: without it the compiler hoists every entry's
         // decoded address out of the sweep loop, three registers per entry
-        uint32_t x[3] = {rw[3 * c], rw[3 * c + 1], rw[3 * c + 2]};
-        asm volatile("" : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]));
-        accumulate_packed<L>(h, x, lds);
+        // (an opaque copy would cost three moves per chunk)
+        asm volatile("" : "+v"(rw[3 * c]), "+v"(rw[3 * c + 1]), "+v"(rw[3 * c + 2]));
+        accumulate_packed<L>(h, rw + 3 * c, lds);
       }
     }
     rs->cr = cb + nch;
@@ -640,7 +654,7 @@ __device__ __forceinline__ void compute(const AnnealArgs &a, const Item &it_in, 
   uint32_t later[3];
   uint32_t flips;
   if (draws)
-    flips = draw_flips<L>(RC > 0 ? a.vid[slot] : f.vid, slot, t, a, later);
+    flips = draw_flips<L>(RC > 0 ? a.vid[slot] : f.vid, slot, t, a, th, later);
   else if (RC > 0)
     flips = (rs->flip >> (3u * rs->j + (t & 3u) - 1u)) & 1u;  // sweep t's plane is (t mod 4) - 1
   else
@@ -827,6 +841,8 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
   }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
     const int plane = plane_of(t);
+    const bool draws = plane < 0;
+    const Thr4 th = draws ? sweep_thresholds(a, (uint32_t)t) : Thr4{};
     rs.cr = 0;
     rs.j = 0;
     for (int32_t ph = 0; ph < a.n_phases; ++ph) {
@@ -855,21 +871,21 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
             fetch<L, ENC, FIELD, RC, USE_LDS>(a, itc, lane, fc, plane, lds);
             if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, draws, th, 0u, rw, &rs);
           if (i + 1 >= ie) break;
           if (i + 3 < ie) {
             ita = pre;
             fetch<L, ENC, FIELD, RC, USE_LDS>(a, ita, lane, fa, plane, lds);
             if (i + 4 < ie) pre = ro_item(a.items, i + 4);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, draws, th, 0u, rw, &rs);
           if (i + 2 >= ie) break;
           if (i + 4 < ie) {
             itb = pre;
             fetch<L, ENC, FIELD, RC, USE_LDS>(a, itb, lane, fb, plane, lds);
             if (i + 5 < ie) pre = ro_item(a.items, i + 5);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, itc, lane, fc, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, itc, lane, fc, lds, (uint32_t)t, draws, th, 0u, rw, &rs);
         }
       } else if (kUnrolled) {
         // one item ahead: fa, fb in rotation
@@ -881,14 +897,14 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
             fetch<L, ENC, FIELD, RC, USE_LDS>(a, itb, lane, fb, plane, lds);
             if (i + 2 < ie) pre = ro_item(a.items, i + 2);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, draws, th, 0u, rw, &rs);
           if (i + 1 >= ie) break;
           if (i + 2 < ie) {
             ita = pre;
             fetch<L, ENC, FIELD, RC, USE_LDS>(a, ita, lane, fa, plane, lds);
             if (i + 3 < ie) pre = ro_item(a.items, i + 3);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, itb, lane, fb, lds, (uint32_t)t, draws, th, 0u, rw, &rs);
         }
       } else {
         // one item ahead, rolled: the copy waits for the next item's loads
@@ -899,7 +915,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
             itb = ro_item(a.items, i + 1);
             fetch<L, ENC, FIELD, RC, USE_LDS>(a, itb, lane, fb, plane, lds);
           }
-          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, 0u, rw, &rs);
+          compute<L, ENC, USE_LDS, FIELD, RC, USE_LDS>(a, ita, lane, fa, lds, (uint32_t)t, draws, th, 0u, rw, &rs);
           if (more) {
             ita = itb;
             fa = fb;
@@ -958,7 +974,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
         }
       }
     }
-  }
+    }
   if (threadIdx.x == 0 && s_bar.gap > 0u) atomicMax(a.bar + kBarGap, s_bar.gap);
 }
 
@@ -996,6 +1012,7 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
   }
   for (int64_t t = a.t_begin; t < a.t_end; ++t) {
     const int plane = plane_of(t);
+    const Thr4 th = plane < 0 ? sweep_thresholds(a, (uint32_t)t) : Thr4{};
     for (int32_t ph = 0; ph < a.n_phases; ++ph) {
       // one item ahead, unrolled so fa and fb swap roles without copies
       Item itb;
@@ -1004,13 +1021,13 @@ __global__ __launch_bounds__(W * kWave) void k_anneal_batch(AnnealArgs args) {
           itb = ro_item(a.items, i + 1);
           fetch<L, ENC, FIELD>(a, itb, lane, fb, plane);
         }
-        compute<L, ENC, true, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, w0);
+        compute<L, ENC, true, FIELD>(a, ita, lane, fa, lds, (uint32_t)t, plane < 0, th, w0);
         if (i + 1 >= ie) break;
         if (i + 2 < ie) {
           ita = ro_item(a.items, i + 2);
           fetch<L, ENC, FIELD>(a, ita, lane, fa, plane);
         }
-        compute<L, ENC, true, FIELD>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, w0);
+        compute<L, ENC, true, FIELD>(a, itb, lane, fb, lds, (uint32_t)t, plane < 0, th, w0);
       }
       const bool last_phase = ph + 1 == a.n_phases;
       const int32_t nph = last_phase ? 0 : ph + 1;

@@ -326,7 +326,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="powerlaw1m", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="async", choices=["async", "det"])
-    ap.add_argument("--coloring", default="lf", choices=["ff", "lf"])
+    ap.add_argument("--coloring", default="ni", choices=["ff", "lf", "ni"],
+                    help="first-fit, largest-first, or near-independent parts (async only)")
     ap.add_argument("--sweeps", type=int, default=None, help="override the schedule length")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--graph", action="store_true",
@@ -373,11 +374,10 @@ def main():
     ww = torch.from_numpy(g.w).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    gr = I.Graph(rp, cl, ww, n=g.n, replicas=R,
-                 coloring=I.COLOR_LARGEST_FIRST if args.coloring == "lf" else I.COLOR_FIRST_FIT)
+    colorings = {"ff": I.COLOR_FIRST_FIT, "lf": I.COLOR_LARGEST_FIRST, "ni": I.COLOR_NEAR_INDEPENDENT}
+    gr = I.Graph(rp, cl, ww, n=g.n, replicas=R, coloring=colorings[args.coloring])
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
-    del rp, cl, ww
     info = gr.info()
     print(f"# create {create_s:.2f}s info={info}", file=sys.stderr, flush=True)
     sch = I.make_schedule(args.p_start, 0.0, M)
@@ -468,7 +468,8 @@ def main():
         "config": {"workload": wl["desc"], "name": args.workload, "n": g.n, "nnz": g.nnz,
                    "sweeps": M, "replicas": R, "mode": args.mode, "coloring": args.coloring,
                    "p_start": args.p_start, "async_phases_budget": "1% of edges inside a phase",
-                   "colors": info["n_colors"], "grid": info["grid"], "block": info["block"],
+                   "colors": info["n_colors"], "async_phases": info["async_phases"],
+                   "grid": info["grid"], "block": info["block"],
                    "lds_spins": bool(info["uses_lds"]), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -497,11 +498,20 @@ def main():
         "create_s": create_s,
     }
     if args.extra and args.workload == "powerlaw1m" and mode == I.MODE_ASYNC:
-        # deterministic mode, timed on the same handle for context
+        # deterministic mode for context: on the same handle when its classes
+        # are colour classes, else on a largest-first handle of the same graph
         Md = 200
+        det_col = args.coloring if info["deterministic_ok"] else "lf"
+        gr_main = gr
+        if not info["deterministic_ok"]:
+            gr = I.Graph(rp, cl, ww, n=g.n, replicas=R, coloring=I.COLOR_LARGEST_FIRST)
         tot, per = timed_anneals(2, I.make_schedule(args.p_start, 0.0, Md), I.MODE_DETERMINISTIC, 4000)
         out["deterministic"] = {"sweeps": Md, "us_per_sweep": float(np.mean(per)) / Md * 1e3,
-                                "value": g.n * R * Md * 2 / (tot / 1e3), "coloring": args.coloring}
+                                "value": g.n * R * Md * 2 / (tot / 1e3), "coloring": det_col,
+                                "phases": gr.info()["n_colors"]}
+        if gr is not gr_main:
+            gr.close()
+            gr = gr_main
     if args.extra and args.workload == "powerlaw1m":
         print("# batch4096 leg ...", file=sys.stderr, flush=True)
         out["batch4096"] = batch_leg(I, torch)
@@ -511,7 +521,7 @@ def main():
         out["time_to_cut"] = time_to_cut(I, torch, gr, g, offsets, M, R, mode, [M // 16, M // 8, M // 4, M // 2])
     if args.cpu_budget > 0:
         print("# cpu baseline ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(g, M, 1000, args.cpu_budget, args.coloring == "lf")
+        out["cpu_baseline"] = cpu_baseline(g, M, 1000, args.cpu_budget, args.coloring != "ff")
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
         out["gpu_over_cpu_single_core"] = value / out["cpu_baseline"]["single_core_value"]
     print(json.dumps(out), flush=True)

@@ -119,7 +119,8 @@ typedef enum {
  *   synchronised, and inside a sweep a spin reads each neighbour's value
  *   from this sweep or the previous one, never older.  Work is issued in
  *   phases, runs of consecutive colour classes (a run grows while at most
- *   1 % of the edges lie inside it), and a phase starts only once every
+ *   1 % of the edges lie inside it) or the near-independent parts of
+ *   ISING_COLOR_NEAR_INDEPENDENT, and a phase starts only once every
  *   spin of the previous phase is final: a neighbour in an earlier phase is
  *   read at this sweep's value, one in a later phase at the previous
  *   sweep's, and one in the same phase at either, as the update races with
@@ -130,8 +131,18 @@ typedef enum { ISING_MODE_DETERMINISTIC = 0, ISING_MODE_ASYNC = 1 } ising_mode_t
 
 /* Greedy colouring rule.  FIRST_FIT visits vertices in increasing id;
  * LARGEST_FIRST visits them by decreasing degree, then increasing id.  Each
- * visited vertex takes the smallest colour no coloured neighbour has. */
-typedef enum { ISING_COLOR_FIRST_FIT = 0, ISING_COLOR_LARGEST_FIRST = 1 } ising_coloring_t;
+ * visited vertex takes the smallest colour no coloured neighbour has.
+ * NEAR_INDEPENDENT (ASYNC mode only) replaces the colour classes by the
+ * fewest parts, each with at most 1 % of the edges inside it, that a
+ * first-fit start plus a local search finds, when that is fewer than the
+ * phases of the LARGEST_FIRST runs; each part is then one async phase.
+ * Otherwise the handle keeps the LARGEST_FIRST colouring.  With parts,
+ * DETERMINISTIC anneals return ISING_ERR_INVALID_ARGUMENT. */
+typedef enum {
+  ISING_COLOR_FIRST_FIT = 0,
+  ISING_COLOR_LARGEST_FIRST = 1,
+  ISING_COLOR_NEAR_INDEPENDENT = 2
+} ising_coloring_t;
 
 /* Flip-probability schedule F_p (Sec. IV-B, Algorithm 2: F_p is lowered
  * after every sweep).  A probability p in [0,1] becomes the threshold
@@ -210,8 +221,9 @@ ising_status_t isingUpdateBest(ising_graph_t g, int64_t *cut, void *stream);
  * set.  Host outputs synchronise the stream. */
 ising_status_t isingGetBest(ising_graph_t g, int64_t *best_cut, int8_t *spins, void *stream);
 
-/* Colouring used by DETERMINISTIC mode: color int32 [n] (host), colour of
- * every caller vertex; *n_colors its number of classes. */
+/* Classes of the handle: color int32 [n] (host), the class of every caller
+ * vertex; *n_colors their number.  Colour classes (DETERMINISTIC mode's
+ * order), or the near-independent parts of ISING_COLOR_NEAR_INDEPENDENT. */
 ising_status_t isingGetColoring(ising_graph_t g, int32_t *color, int32_t *n_colors);
 
 /* Sum of w over undirected edges (W in 2 cut = W - E). */
@@ -258,6 +270,8 @@ typedef struct {
   int32_t resident_edges;   /* cooperative launch: bit m set if mode m (0 deterministic, 1 async)
                                reads the +-1 edge entries from HBM once per call and keeps them
                                in registers (3 bytes each) for all its sweeps */
+  int32_t async_phases;     /* phases of an async sweep (runs of classes) */
+  int32_t deterministic_ok; /* 1 if the classes are colour classes (DETERMINISTIC mode allowed) */
 } ising_info_t;
 
 ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info);

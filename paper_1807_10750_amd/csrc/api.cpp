@@ -89,6 +89,7 @@ struct ising_graph_s {
   int32_t R = 1;
   int32_t n_colors = 0;
   std::vector<int32_t> color;
+  bool proper_classes = true;  // classes are colour classes (false: near-independent parts)
   int64_t W = 0;
   HostLayout lay;            // host copy (entries/wts released after upload)
   int64_t entry_bytes = 0;   // edge stream bytes per sweep (entries + weights)
@@ -419,6 +420,9 @@ ising_status_t internal_check_anneal(ising_graph_t g, const ising_schedule_t *s,
   if (g == nullptr || s == nullptr) return fail(ISING_ERR_INVALID_ARGUMENT, "NULL argument");
   if (mode != ISING_MODE_DETERMINISTIC && mode != ISING_MODE_ASYNC)
     return fail(ISING_ERR_INVALID_ARGUMENT, "unknown mode");
+  if (mode == ISING_MODE_DETERMINISTIC && !g->proper_classes)
+    return fail(ISING_ERR_INVALID_ARGUMENT,
+                "deterministic mode needs colour classes; this handle holds near-independent parts (async only)");
   if (s->n_sweeps < 1 || s->n_sweeps > ((int64_t)1 << 32))
     return fail(ISING_ERR_INVALID_ARGUMENT, "n_sweeps must be in [1, 2^32]");
   if (s->kind == ISING_SCHED_LINEAR) {
@@ -517,7 +521,8 @@ ising_status_t create_impl(ising_graph_t *out, int64_t n, int64_t nnz, const int
   if (row_ptr == nullptr || (nnz > 0 && (col == nullptr || w == nullptr)))
     return fail(ISING_ERR_INVALID_ARGUMENT, "graph pointer is NULL");
   if (n_replicas < 1) return fail(ISING_ERR_INVALID_ARGUMENT, "n_replicas < 1");
-  if (coloring != ISING_COLOR_FIRST_FIT && coloring != ISING_COLOR_LARGEST_FIRST)
+  if (coloring != ISING_COLOR_FIRST_FIT && coloring != ISING_COLOR_LARGEST_FIRST &&
+      coloring != ISING_COLOR_NEAR_INDEPENDENT)
     return fail(ISING_ERR_INVALID_ARGUMENT, "unknown colouring");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (is_device_ptr(row_ptr) || is_device_ptr(col) || is_device_ptr(w)) {
@@ -566,8 +571,23 @@ ising_status_t create_impl(ising_graph_t *out, int64_t n, int64_t nnz, const int
   } catch (const std::bad_alloc &) {
     return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed for the row sums"));
   }
+  // budget of edges inside one async phase (ISING_ASYNC_MERGE, in units of
+  // 0.1 % of the edges)
+  const double merge_budget = 0.001 * (double)std::max<int64_t>(0, env_int("ISING_ASYNC_MERGE", kAsyncMergeBudget));
   try {
-    g->n_colors = greedy_coloring(csr, coloring == ISING_COLOR_LARGEST_FIRST, &g->color);
+    g->n_colors = greedy_coloring(csr, coloring != ISING_COLOR_FIRST_FIT, &g->color);
+    if (coloring == ISING_COLOR_NEAR_INDEPENDENT && n > 0) {
+      // fewer async phases than the largest-first colouring's runs, each
+      // within the same budget; otherwise the colouring stays
+      const int32_t runs = (int32_t)phase_runs(csr, g->color, g->n_colors, merge_budget).size() - 1;
+      std::vector<int32_t> part;
+      const int32_t K = near_independent_parts(csr, merge_budget, runs - 1, &part);
+      if (K > 0) {
+        g->color.swap(part);
+        g->n_colors = K;
+        g->proper_classes = false;
+      }
+    }
   } catch (const std::bad_alloc &) {
     return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed while colouring"));
   }
@@ -652,10 +672,8 @@ ising_status_t create_impl(ising_graph_t *out, int64_t n, int64_t nnz, const int
   g->grid = grid;
   g->nw = grid * waves_per_block;
   // phase tables: deterministic = one colour class per phase; async merges
-  // consecutive classes while the edges inside a phase stay within a budget
-  // (ISING_ASYNC_MERGE, in units of 0.1 % of the edges)
+  // consecutive classes while the edges inside a phase stay within the budget
   std::vector<uint32_t> wave_ptr[2], cls_w64[2];
-  const double merge_budget = 0.001 * (double)std::max<int64_t>(0, env_int("ISING_ASYNC_MERGE", kAsyncMergeBudget));
   for (int m = 0; m < 2; ++m) {
     std::vector<int32_t> pc;
     if (m == 0) {
@@ -900,6 +918,8 @@ ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info) {
     info->max_sweep_gap = (int32_t)gap;
   }
   info->resident_edges = (g->res_edges[0] ? 1 : 0) | (g->res_edges[1] ? 2 : 0);
+  info->async_phases = g->batch ? g->n_colors : g->n_phases[1];
+  info->deterministic_ok = g->proper_classes ? 1 : 0;
   info->pm1 = g->lay.enc == kEncPm1 ? 1 : 0;
   info->encoding = g->lay.enc;
   info->edge_bytes = g->entry_bytes;

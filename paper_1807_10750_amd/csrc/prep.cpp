@@ -129,6 +129,94 @@ int32_t greedy_coloring(const HostCSR &g, bool largest_first, std::vector<int32_
   return n_colors;
 }
 
+int32_t near_independent_parts(const HostCSR &g, double budget, int32_t max_parts, std::vector<int32_t> *part) {
+  const int64_t n = g.n;
+  const int64_t *rp = g.row_ptr;
+  std::vector<int32_t> &pt = *part;
+  pt.assign(n, 0);
+  max_parts = std::min(max_parts, kMaxParts);
+  // visit order: degree descending, id ascending
+  int64_t maxdeg = 0;
+  for (int64_t v = 0; v < n; ++v) maxdeg = std::max(maxdeg, rp[v + 1] - rp[v]);
+  std::vector<int32_t> visit(n);
+  {
+    std::vector<int64_t> start(maxdeg + 2, 0);
+    for (int64_t v = 0; v < n; ++v) ++start[maxdeg - (rp[v + 1] - rp[v]) + 1];
+    for (int64_t d = 0; d <= maxdeg; ++d) start[d + 1] += start[d];
+    for (int64_t v = 0; v < n; ++v) visit[start[maxdeg - (rp[v + 1] - rp[v])]++] = (int32_t)v;
+  }
+  // directed entries allowed inside one part (an undirected edge is two)
+  const double limit = budget * (double)g.nnz;
+  // one attempt at K parts, left in pt; true when every part fits
+  auto attempt = [&](int32_t K) {
+    // first fit into parts 0 .. K-2, which start out independent; a vertex
+    // with a neighbour in each of them goes to part K-1
+    pt.assign(n, -1);
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t v = visit[i];
+      uint32_t used = 0;
+      for (int64_t k = rp[v]; k < rp[v + 1]; ++k) {
+        const int32_t q = pt[g.col[k]];
+        if (q >= 0) used |= 1u << q;
+      }
+      int32_t q = 0;
+      while (q < K - 1 && (used >> q) & 1u) ++q;
+      pt[v] = q;
+    }
+    int64_t inside[kMaxParts] = {};
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t k = rp[v]; k < rp[v + 1]; ++k) inside[pt[v]] += pt[g.col[k]] == pt[v] ? 1 : 0;
+    auto worst = [&]() {
+      int64_t m = 0;
+      for (int32_t q = 0; q < K; ++q) m = std::max(m, inside[q]);
+      return m;
+    };
+    // local search: each vertex in turn moves to the part where it has the
+    // fewest neighbours, counted with a weight per part that grows while
+    // the part holds more inside edges than the mean; it stops once every
+    // part fits, or after kPartPasses passes, or when the fullest part has
+    // not shrunk for kPartStall passes
+    double wt[kMaxParts];
+    for (int32_t q = 0; q < K; ++q) wt[q] = 1.0;
+    int64_t best = worst();
+    int stall = 0;
+    for (int pass = 0; pass < kPartPasses && (double)worst() > limit && stall < kPartStall; ++pass) {
+      for (int64_t i = 0; i < n; ++i) {
+        const int32_t v = visit[i];
+        int64_t cnt[kMaxParts] = {};
+        for (int64_t k = rp[v]; k < rp[v + 1]; ++k) ++cnt[pt[g.col[k]]];
+        const int32_t cur = pt[v];
+        int32_t to = cur;
+        for (int32_t q = 0; q < K; ++q)
+          if (wt[q] * (double)cnt[q] < wt[to] * (double)cnt[to]) to = q;
+        if (to != cur) {
+          inside[cur] -= 2 * cnt[cur];
+          inside[to] += 2 * cnt[to];
+          pt[v] = to;
+        }
+      }
+      double mean = 0.0;
+      for (int32_t q = 0; q < K; ++q) mean += (double)inside[q] / K;
+      for (int32_t q = 0; q < K; ++q) wt[q] *= (double)inside[q] > mean ? 1.05 : 0.97;
+      const int64_t m = worst();
+      stall = m < best ? 0 : stall + 1;
+      best = std::min(best, m);
+    }
+    return (double)worst() <= limit;
+  };
+  // from max_parts down while the parts still fit
+  int32_t found = 0;
+  std::vector<int32_t> keep;
+  for (int32_t K = max_parts; K >= 1; --K) {
+    if (!attempt(K)) break;
+    found = K;
+    keep.swap(pt);
+  }
+  if (found > 0) pt.swap(keep);
+  else pt.assign(n, 0);
+  return found;
+}
+
 int choose_encoding(const HostCSR &g, int64_t n_slots) {
   bool pm1 = true;
   for (int64_t k = 0; k < g.nnz; ++k)

@@ -39,6 +39,19 @@ int validate_graph(const HostCSR &g, int64_t *W_out, std::string *msg);
 // already-coloured neighbours.
 int32_t greedy_coloring(const HostCSR &g, bool largest_first, std::vector<int32_t> *color);
 
+// Near-independent parts for the async sweep (not a colouring): K parts,
+// each with at most budget * nnz directed entries inside it, for the
+// smallest K reached counting down from max_parts (at most kMaxParts) before
+// an attempt fails.  An attempt at K visits vertices by (degree desc, id
+// asc), fills parts 0 .. K-2 first fit as independent sets and puts the rest
+// in part K-1, then runs local-search passes that move each vertex to the
+// part where it has the fewest (weighted) neighbours.  Returns K and writes
+// each vertex's part, or 0 (all parts 0) when not even max_parts fits.
+constexpr int32_t kMaxParts = 16;
+constexpr int kPartPasses = 32;
+constexpr int kPartStall = 4;
+int32_t near_independent_parts(const HostCSR &g, double budget, int32_t max_parts, std::vector<int32_t> *part);
+
 struct HostLayout {
   int64_t n_slots = 0;                 // multiple of 64
   int32_t n_phases = 0;                // colours

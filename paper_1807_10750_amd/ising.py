@@ -32,6 +32,7 @@ MODE_DETERMINISTIC = 0
 MODE_ASYNC = 1
 COLOR_FIRST_FIT = 0
 COLOR_LARGEST_FIRST = 1
+COLOR_NEAR_INDEPENDENT = 2
 SCHED_LINEAR = 0
 SCHED_EXPLICIT = 1
 
@@ -61,7 +62,8 @@ class Info(ctypes.Structure):
                 ("pm1", ctypes.c_int32), ("encoding", ctypes.c_int32), ("edge_bytes", ctypes.c_int64),
                 ("vertex_bytes", ctypes.c_int64), ("spin_bytes", ctypes.c_int64),
                 ("items", ctypes.c_int64), ("bins", ctypes.c_int32), ("max_sweep_gap", ctypes.c_int32),
-                ("resident_edges", ctypes.c_int32)]
+                ("resident_edges", ctypes.c_int32), ("async_phases", ctypes.c_int32),
+                ("deterministic_ok", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -121,6 +121,65 @@ void exercise(const Graph &G0, bool batched, int L) {
   }
 }
 
+// Near-independent parts: every part within the budget, the fewest parts
+// the search finds (one fewer finds none), the same result on a second call.
+void parts(const Graph &G0) {
+  HostCSR g = G0.csr();
+  for (double budget : {0.0, 0.01, 0.05}) {
+    std::vector<int32_t> pt, again;
+    const int32_t K = near_independent_parts(g, budget, kMaxParts, &pt);
+    expect(K >= 1 || g.nnz > 0, "an empty graph is one part");
+    if (K == 0) continue;
+    std::vector<int64_t> inside((size_t)K, 0);
+    for (int64_t v = 0; v < g.n; ++v) {
+      expect(pt[(size_t)v] >= 0 && pt[(size_t)v] < K, "part in range");
+      for (int64_t k = g.row_ptr[v]; k < g.row_ptr[v + 1]; ++k)
+        inside[(size_t)pt[(size_t)v]] += pt[(size_t)v] == pt[(size_t)g.col[k]] ? 1 : 0;
+    }
+    for (int32_t q = 0; q < K; ++q) expect((double)inside[(size_t)q] <= budget * (double)g.nnz, "part within budget");
+    if (K > 1) expect(near_independent_parts(g, budget, K - 1, &again) == 0, "no fewer parts found");
+    expect(near_independent_parts(g, budget, K, &again) == K && again == pt, "same parts again");
+  }
+}
+
+Graph from_edges(int64_t n, const std::vector<std::pair<int32_t, int32_t>> &edges) {
+  std::vector<std::vector<int32_t>> adj((size_t)n);
+  for (auto &e : edges) {
+    adj[(size_t)e.first].push_back(e.second);
+    adj[(size_t)e.second].push_back(e.first);
+  }
+  Graph g;
+  g.n = n;
+  g.rp.assign((size_t)n + 1, 0);
+  for (int64_t v = 0; v < n; ++v) {
+    g.rp[(size_t)v + 1] = g.rp[(size_t)v] + (int64_t)adj[(size_t)v].size();
+    for (int32_t u : adj[(size_t)v]) {
+      g.col.push_back(u);
+      g.w.push_back(1);
+    }
+  }
+  return g;
+}
+
+void parts_known() {
+  std::vector<int32_t> pt;
+  // with no edge allowed inside a part: a triangle needs 3, an even cycle 2
+  expect(near_independent_parts(from_edges(3, {{0, 1}, {1, 2}, {2, 0}}).csr(), 0.0, 16, &pt) == 3, "triangle: 3 parts");
+  std::vector<std::pair<int32_t, int32_t>> cyc;
+  for (int32_t v = 0; v < 10; ++v) cyc.push_back({v, (v + 1) % 10});
+  expect(near_independent_parts(from_edges(10, cyc).csr(), 0.0, 16, &pt) == 2, "even cycle: 2 parts");
+  // a triangle with a third of its edges allowed inside a part: 2 parts
+  expect(near_independent_parts(from_edges(3, {{0, 1}, {1, 2}, {2, 0}}).csr(), 1.0 / 3.0, 16, &pt) == 2,
+         "triangle, one edge allowed: 2 parts");
+  // K_5 with no edge allowed cannot be split into 4
+  std::vector<std::pair<int32_t, int32_t>> k5;
+  for (int32_t a = 0; a < 5; ++a)
+    for (int32_t b = a + 1; b < 5; ++b) k5.push_back({a, b});
+  expect(near_independent_parts(from_edges(5, k5).csr(), 0.0, 4, &pt) == 0, "K5: not 4 parts");
+  expect(near_independent_parts(from_edges(5, k5).csr(), 0.0, 16, &pt) == 5, "K5: 5 parts");
+  expect(near_independent_parts(from_edges(4, {}).csr(), 0.0, 16, &pt) == 1, "no edges: 1 part");
+}
+
 void bad_inputs() {
   // structure, self-loop, duplicate, asymmetry, overflow: each reported
   Graph g = random_graph(50, 120, 0, true, 7);
@@ -165,6 +224,11 @@ int main() {
   exercise(random_graph(700, 2000, 2, false, 3), false, 4);
   exercise(random_graph(3000, 9000, 3, true, 4), false, 32);
   exercise(random_graph(2000, 1500, 0, true, 5), true, 8);  // many components
+  parts(random_graph(0, 0, 0, true, 1));
+  parts(random_graph(700, 2000, 2, true, 2));
+  parts(random_graph(3000, 9000, 3, true, 4));
+  parts(random_graph(2000, 1500, 0, true, 5));
+  parts_known();
   if (failures) {
     std::fprintf(stderr, "%d failures\n", failures);
     return 1;

@@ -2,6 +2,7 @@
 #include "prep.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <limits>
 #include <new>
@@ -172,15 +173,26 @@ int32_t near_independent_parts(const HostCSR &g, double budget, int32_t max_part
       return m;
     };
     // local search: each vertex in turn moves to the part where it has the
-    // fewest neighbours, counted with a weight per part that grows while
-    // the part holds more inside edges than the mean; it stops once every
-    // part fits, or after kPartPasses passes, or when the fullest part has
-    // not shrunk for kPartStall passes
+    // fewest neighbours, counted with a weight per part that grows while the
+    // part holds more inside edges than the mean.  When no part is better, a
+    // random other part is taken with probability exp(-d / T) (d: the
+    // weighted increase), T falling linearly to 0 over kPartPasses passes
+    // (annealing, with a fixed-seed xorshift).  It stops once every part
+    // fits, or after kPartPasses passes, or half way when the fullest part
+    // has never come within twice the limit.
     double wt[kMaxParts];
     for (int32_t q = 0; q < K; ++q) wt[q] = 1.0;
+    uint64_t rng = 0x9E3779B97F4A7C15ull ^ (uint64_t)K;
+    auto next = [&]() {
+      rng ^= rng << 13;
+      rng ^= rng >> 7;
+      rng ^= rng << 17;
+      return rng;
+    };
     int64_t best = worst();
-    int stall = 0;
-    for (int pass = 0; pass < kPartPasses && (double)worst() > limit && stall < kPartStall; ++pass) {
+    for (int pass = 0; pass < kPartPasses && (double)worst() > limit; ++pass) {
+      if (pass >= kPartPasses / 2 && (double)best > 2.0 * limit) break;
+      const double T = kPartT0 * (1.0 - (double)pass / kPartPasses);
       for (int64_t i = 0; i < n; ++i) {
         const int32_t v = visit[i];
         int64_t cnt[kMaxParts] = {};
@@ -189,6 +201,12 @@ int32_t near_independent_parts(const HostCSR &g, double budget, int32_t max_part
         int32_t to = cur;
         for (int32_t q = 0; q < K; ++q)
           if (wt[q] * (double)cnt[q] < wt[to] * (double)cnt[to]) to = q;
+        if (to == cur && K > 1) {
+          const int32_t q = (int32_t)(next() % (uint64_t)K);
+          const double d = wt[q] * (double)cnt[q] - wt[cur] * (double)cnt[cur];
+          const double u = (double)(next() >> 11) * (1.0 / 9007199254740992.0);
+          if (q != cur && (d <= 0.0 || (T > 0.0 && u < std::exp(-d / T)))) to = q;
+        }
         if (to != cur) {
           inside[cur] -= 2 * cnt[cur];
           inside[to] += 2 * cnt[to];
@@ -198,9 +216,7 @@ int32_t near_independent_parts(const HostCSR &g, double budget, int32_t max_part
       double mean = 0.0;
       for (int32_t q = 0; q < K; ++q) mean += (double)inside[q] / K;
       for (int32_t q = 0; q < K; ++q) wt[q] *= (double)inside[q] > mean ? 1.05 : 0.97;
-      const int64_t m = worst();
-      stall = m < best ? 0 : stall + 1;
-      best = std::min(best, m);
+      best = std::min(best, worst());
     }
     return (double)worst() <= limit;
   };

@@ -44,12 +44,13 @@ int32_t greedy_coloring(const HostCSR &g, bool largest_first, std::vector<int32_
 // smallest K reached counting down from max_parts (at most kMaxParts) before
 // an attempt fails.  An attempt at K visits vertices by (degree desc, id
 // asc), fills parts 0 .. K-2 first fit as independent sets and puts the rest
-// in part K-1, then runs local-search passes that move each vertex to the
-// part where it has the fewest (weighted) neighbours.  Returns K and writes
-// each vertex's part, or 0 (all parts 0) when not even max_parts fits.
+// in part K-1, then runs annealed local-search passes that move each vertex
+// to the part where it has the fewest (weighted) neighbours.  Deterministic.
+// Returns K and writes each vertex's part, or 0 (all parts 0) when not even
+// max_parts fits.
 constexpr int32_t kMaxParts = 16;
-constexpr int kPartPasses = 32;
-constexpr int kPartStall = 4;
+constexpr int kPartPasses = 64;
+constexpr double kPartT0 = 0.5;
 int32_t near_independent_parts(const HostCSR &g, double budget, int32_t max_parts, std::vector<int32_t> *part);
 
 struct HostLayout {

@@ -80,7 +80,8 @@
  *       ISING_BIN_SHIFT=k       lanes per row chosen for degree >> k
  *       ISING_WIDE=1            the separate int8 weight stream for all
  *                               general weights
- *       ISING_RESIDENT_EDGES=0  never keep +-1 entries in registers
+ *       ISING_RESIDENT_EDGES=0  never keep +-1 entries in registers; =24 only in
+ *                               the larger (24-chunk) register variant
  *       ISING_ASYNC_MERGE=b     async phases merge classes while at most
  *                               b/1000 of the edges lie inside (default 10)
  *       ISING_BARRIER_POLLS=p   polls before a wait gives up (isingAnneal)
@@ -271,6 +272,7 @@ typedef struct {
                                reads the +-1 edge entries from HBM once per call and keeps them
                                in registers (3 bytes each) for all its sweeps */
   int32_t async_phases;     /* phases of an async sweep (runs of classes) */
+  int32_t resident_chunks;  /* chunks per lane of the register variant in use, 18 or 24 (0: none) */
   int32_t deterministic_ok; /* 1 if the classes are colour classes (DETERMINISTIC mode allowed) */
 } ising_info_t;
 

@@ -115,7 +115,7 @@ struct ising_graph_s {
   size_t batch_lds = 0;
   uint32_t *d_bin_wave_ptr = nullptr;            // [n_bins][colours][waves + 1]
   uint32_t *d_bin_words = nullptr;               // [n_bins + 1]
-  bool res_edges[2] = {false, false};             // per mode: entries held in registers (kResChunks)
+  int res_edges[2] = {0, 0};  // per mode: chunks of the register-resident variant (0: entries streamed)
   uint32_t *d_cls_w64[2] = {nullptr, nullptr};   // per mode: phase -> spin word range
   int32_t n_phases[2] = {0, 0};
   uint32_t *d_spins = nullptr;
@@ -688,11 +688,16 @@ ising_status_t create_impl(ising_graph_t *out, int64_t n, int64_t nnz, const int
     g->n_phases[m] = (int32_t)pc.size() - 1;
     wave_ptr[m] = rotate_ranges(partition_waves(lay, pc, g->nw, true), g->n_phases[m], g->nw, waves_per_block);
     // register-resident entries when every wavefront's items fit them
-    if (!g->batch && g->use_lds && L == 1 && lay.enc == kEncPm1 && lay.n_slots <= kResMaxSlots &&
-        env_int("ISING_RESIDENT_EDGES", 1) != 0) {
+    // (the smaller variant when it is enough; ISING_RESIDENT_EDGES=24 takes
+    // the larger one, =0 neither)
+    const int64_t res_knob = env_int("ISING_RESIDENT_EDGES", 1);
+    if (!g->batch && g->use_lds && L == 1 && lay.enc == kEncPm1 && lay.n_slots <= kResMaxSlots && res_knob != 0) {
       uint64_t items = 0;
       const uint64_t chunks = max_wave_chunks(lay, wave_ptr[m], g->n_phases[m], g->nw, &items);
-      g->res_edges[m] = chunks <= (uint64_t)kResChunks && items <= (uint64_t)kResMaxItems;
+      if (items <= (uint64_t)kResMaxItems)
+        g->res_edges[m] = chunks <= (uint64_t)kResChunksSmall && res_knob != kResChunks ? kResChunksSmall
+                          : chunks <= (uint64_t)kResChunks                              ? kResChunks
+                                                                                        : 0;
     }
     cls_w64[m].resize(pc.size());
     for (size_t p = 0; p < pc.size(); ++p) cls_w64[m][p] = (uint32_t)((uint64_t)lay.cls_begin[pc[p]] * L / 64);
@@ -918,6 +923,7 @@ ising_status_t isingGetInfo(ising_graph_t g, ising_info_t *info) {
     info->max_sweep_gap = (int32_t)gap;
   }
   info->resident_edges = (g->res_edges[0] ? 1 : 0) | (g->res_edges[1] ? 2 : 0);
+  info->resident_chunks = std::max(g->res_edges[0], g->res_edges[1]);
   info->async_phases = g->batch ? g->n_colors : g->n_phases[1];
   info->deterministic_ok = g->proper_classes ? 1 : 0;
   info->pm1 = g->lay.enc == kEncPm1 ? 1 : 0;

@@ -17,6 +17,10 @@ constexpr size_t kLdsBudget = 160 * 1024 - 2048;
 // bit per slot, LDS mirror): chunks of four entries each lane holds, three
 // registers per chunk.  Slots must fit the 23 bits of a packed entry.
 constexpr int kResChunks = 24;
+// A smaller variant for graphs whose wavefronts hold at most this many: the
+// registers it leaves free let the phase-end copy keep twice the loads in
+// flight.
+constexpr int kResChunksSmall = 18;
 // Items per wavefront in that variant: each keeps its row spin and three
 // flip bits per lane in two registers (one bit and three bits per item).
 constexpr int kResMaxItems = 10;
@@ -24,9 +28,10 @@ constexpr int64_t kResMaxSlots = int64_t(1) << 23;
 template <int L, int ENC, bool USE_LDS>
 constexpr bool kHasResident = L == 1 && ENC == kEncPm1 && USE_LDS;
 
-// resident: the kResChunks variant; every wavefront's items must then hold
-// at most kResChunks chunks per lane in total (ceil(len4 / g) per item).
-hipError_t launch_anneal(int L, int enc, bool use_lds, bool resident, const AnnealArgs &a, int grid,
+// res_chunks: 0, or the register-resident variant (kResChunksSmall or
+// kResChunks); every wavefront's items must then hold at most that many
+// chunks per lane in total (ceil(len4 / g) per item).
+hipError_t launch_anneal(int L, int enc, bool use_lds, int res_chunks, const AnnealArgs &a, int grid,
                          size_t lds_bytes, hipStream_t s);
 // Batched anneal: grid = n_bins x replica groups, waves per workgroup in {4, 8, 16}.
 hipError_t launch_anneal_batch(int L, int enc, int waves, const AnnealArgs &a, int grid, size_t lds_bytes,

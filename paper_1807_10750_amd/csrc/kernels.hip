@@ -948,9 +948,9 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           ita = ro_item(a.items, ib);
           fetch<L, ENC, FIELD, RC, USE_LDS>(a, ita, lane, fa, next_plane, lds);
         }
-        // (the register-resident variant has fewer registers to spare)
-        if (!done &&
-            !xch_phase_end<(RC > 0 ? 4u : 8u)>(a, lds, ph, last_phase, (uint32_t)(t - a.t_begin + 1), epoch, s_bar))
+        // (the larger register-resident variant has fewer registers to spare)
+        if (!done && !xch_phase_end<(RC > kResChunksSmall ? 4u : 8u)>(a, lds, ph, last_phase,
+                                                                      (uint32_t)(t - a.t_begin + 1), epoch, s_bar))
           return;
       } else if (multi) {
         // without the LDS copy: a grid barrier ends every phase
@@ -1300,13 +1300,14 @@ hipError_t occupancy_t(int *blocks, size_t lds_bytes) {
   *blocks = b0 < b1 ? b0 : b1;
   if constexpr (kHasResident<L, ENC, USE_LDS>) {
     // and the register-resident variants
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &b0, reinterpret_cast<const void *>(k_anneal<L, ENC, USE_LDS, false, kResChunks>), kAnnealBlock, 0);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &b1, reinterpret_cast<const void *>(k_anneal<L, ENC, USE_LDS, true, kResChunks>), kAnnealBlock, 0);
-    *blocks = std::min(*blocks, std::min(b0, b1));
+    const void *res[4] = {reinterpret_cast<const void *>(k_anneal<L, ENC, USE_LDS, false, kResChunks>),
+                          reinterpret_cast<const void *>(k_anneal<L, ENC, USE_LDS, true, kResChunks>),
+                          reinterpret_cast<const void *>(k_anneal<L, ENC, USE_LDS, false, kResChunksSmall>),
+                          reinterpret_cast<const void *>(k_anneal<L, ENC, USE_LDS, true, kResChunksSmall>)};
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, res[k], kAnnealBlock, 0);
+      *blocks = std::min(*blocks, b0);
+    }
   }
   return e;
 }
@@ -1326,12 +1327,16 @@ hipError_t occupancy_t(int *blocks, size_t lds_bytes) {
 
 namespace {
 template <int L, int ENC>
-hipError_t anneal_LE(const AnnealArgs &a, bool use_lds, bool resident, int grid, size_t lds, hipStream_t s) {
-  if (resident) {
+hipError_t anneal_LE(const AnnealArgs &a, bool use_lds, int res_chunks, int grid, size_t lds, hipStream_t s) {
+  if (res_chunks != 0) {
     if constexpr (kHasResident<L, ENC, true>) {
       if (!use_lds) return hipErrorInvalidValue;
-      return a.bias != nullptr ? launch_anneal_t<L, ENC, true, true, kResChunks>(a, grid, lds, s)
-                               : launch_anneal_t<L, ENC, true, false, kResChunks>(a, grid, lds, s);
+      if (res_chunks == kResChunksSmall)
+        return a.bias != nullptr ? launch_anneal_t<L, ENC, true, true, kResChunksSmall>(a, grid, lds, s)
+                                 : launch_anneal_t<L, ENC, true, false, kResChunksSmall>(a, grid, lds, s);
+      if (res_chunks == kResChunks)
+        return a.bias != nullptr ? launch_anneal_t<L, ENC, true, true, kResChunks>(a, grid, lds, s)
+                                 : launch_anneal_t<L, ENC, true, false, kResChunks>(a, grid, lds, s);
     }
     return hipErrorInvalidValue;
   }
@@ -1342,10 +1347,10 @@ hipError_t anneal_LE(const AnnealArgs &a, bool use_lds, bool resident, int grid,
                  : launch_anneal_t<L, ENC, false, false>(a, grid, lds, s);
 }
 template <int L>
-hipError_t anneal_L(const AnnealArgs &a, int enc, bool use_lds, bool resident, int grid, size_t lds, hipStream_t s) {
-  if (enc == kEncPm1) return anneal_LE<L, kEncPm1>(a, use_lds, resident, grid, lds, s);
-  if (enc == kEncW8) return anneal_LE<L, kEncW8>(a, use_lds, resident, grid, lds, s);
-  return anneal_LE<L, kEncWide>(a, use_lds, resident, grid, lds, s);
+hipError_t anneal_L(const AnnealArgs &a, int enc, bool use_lds, int res_chunks, int grid, size_t lds, hipStream_t s) {
+  if (enc == kEncPm1) return anneal_LE<L, kEncPm1>(a, use_lds, res_chunks, grid, lds, s);
+  if (enc == kEncW8) return anneal_LE<L, kEncW8>(a, use_lds, res_chunks, grid, lds, s);
+  return anneal_LE<L, kEncWide>(a, use_lds, res_chunks, grid, lds, s);
 }
 template <int L, int ENC>
 hipError_t batch_LE(const AnnealArgs &a, int waves, int grid, size_t lds, hipStream_t s) {
@@ -1420,9 +1425,9 @@ hipError_t launch_best(const unsigned long long *sums, int32_t R, int32_t L, int
   return hipGetLastError();
 }
 
-hipError_t launch_anneal(int L, int enc, bool use_lds, bool resident, const AnnealArgs &a, int grid,
+hipError_t launch_anneal(int L, int enc, bool use_lds, int res_chunks, const AnnealArgs &a, int grid,
                          size_t lds_bytes, hipStream_t s) {
-  ISING_DISPATCH_L(L, anneal_L, a, enc, use_lds, resident, grid, lds_bytes, s);
+  ISING_DISPATCH_L(L, anneal_L, a, enc, use_lds, res_chunks, grid, lds_bytes, s);
 }
 
 hipError_t launch_anneal_batch(int L, int enc, int waves, const AnnealArgs &a, int grid, size_t lds_bytes,

@@ -63,6 +63,7 @@ class Info(ctypes.Structure):
                 ("vertex_bytes", ctypes.c_int64), ("spin_bytes", ctypes.c_int64),
                 ("items", ctypes.c_int64), ("bins", ctypes.c_int32), ("max_sweep_gap", ctypes.c_int32),
                 ("resident_edges", ctypes.c_int32), ("async_phases", ctypes.c_int32),
+                ("resident_chunks", ctypes.c_int32),
                 ("deterministic_ok", ctypes.c_int32)]
 
     def as_dict(self):

@@ -76,16 +76,19 @@ def test_resident_deterministic_bit_exact(I, knobs):
     g = G.powerlaw_chung_lu(6000, max_deg=500, seed=12)
     M, seed, chunks = 25, 13, [0, 1, 9, 25]
     so, (Co, Eo) = oracle_spins(g, seed, M, M)
-    flags = {}
-    for res in (1, 0):
+    flags, width = {}, {}
+    # 1: the smallest register variant that holds the items, 24: the larger
+    # one, 0: entries streamed
+    for res in (1, 24, 0):
         print(f"[resident] n={g.n} knobs={knobs} resident={res}", flush=True)
         s, c, e, info = gpu_det(I, g, seed, M, chunks, dict(ISING_RESIDENT_EDGES=res, **knobs))
-        flags[res] = info["resident_edges"]
+        flags[res], width[res] = info["resident_edges"], info["resident_chunks"]
         bad = np.argwhere(s != so)
         assert len(bad) == 0, f"resident={res}: {len(bad)} spins differ, first {bad[:5].tolist()}; info={info}"
         assert np.array_equal(c, Co) and np.array_equal(e, Eo)
     assert flags[1] & 1, "the registers should hold this layout"
-    assert flags[0] == 0
+    assert width[1] in (18, 24) and width[24] == 24
+    assert flags[0] == 0 and width[0] == 0
 
 
 def test_resident_off_when_items_do_not_fit(I):

@@ -86,6 +86,17 @@ __device__ __forceinline__ uint32_t ld_coherent(const uint32_t *p) {
 __device__ __forceinline__ unsigned long long ld_coherent64(const unsigned long long *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Agent-coherent 16-byte load of exchange words 2q and 2q + 1 through a
+// buffer resource over the exchange array (cache policy sc1, the one the
+// agent-scope loads above get; volatile, so a re-poll is never merged with
+// an earlier load; past the array the hardware returns zeros).
+constexpr int kCpolSc1Volatile = 16 | (1 << 31);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t xch_rsrc(const unsigned long long *xch, uint32_t n_words) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned long long *>(xch), 0, n_words * 8u, 0x00020000);
+}
+__device__ __forceinline__ uint4 ld_coherent_pair(__amdgpu_buffer_rsrc_t r, uint32_t q) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, q * 16u, 0, kCpolSc1Volatile));
+}
 __device__ __forceinline__ uint32_t ld_workgroup(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -401,23 +412,35 @@ __device__ __forceinline__ bool xch_phase_end(const AnnealArgs &a, uint32_t *lds
     return (hi & 0x3FFFFFFu) == (hi >> 26) * k;
   };
   bool ok = true;
-  const uint32_t b = 2u * ro(a.cls_w64, ph), e = 2u * ro(a.cls_w64, ph + 1);
-  for (uint32_t i0 = b + tid; ok && i0 < e; i0 += XB * nt) {
-    unsigned long long v[XB];
+  // the phase's words come in pairs (its range is whole 64-bit units of the
+  // spin state): 16-byte loads, XB / 2 in flight per thread, and an 8-byte
+  // LDS write when both words are complete
+  constexpr uint32_t XP = XB / 2;
+  const uint32_t qb = ro(a.cls_w64, ph), qe = ro(a.cls_w64, ph + 1);
+  const __amdgpu_buffer_rsrc_t rs = xch_rsrc(a.xch, a.n_words);
+  auto put = [&](uint32_t q, const uint4 &v, uint32_t &pend, uint32_t j) {
+    const bool c0 = ((pend >> (2 * j)) & 1u) && complete(((unsigned long long)v.y << 32) | v.x);
+    const bool c1 = ((pend >> (2 * j + 1)) & 1u) && complete(((unsigned long long)v.w << 32) | v.z);
+    if (c0 && c1) {
+      *reinterpret_cast<uint2 *>(lds + 2 * q) = make_uint2(v.x, v.z);
+    } else {
+      if (c0) lds[2 * q] = v.x;
+      if (c1) lds[2 * q + 1] = v.z;
+    }
+    pend &= ~(((c0 ? 1u : 0u) | (c1 ? 2u : 0u)) << (2 * j));
+  };
+  for (uint32_t q0 = qb + tid; ok && q0 < qe; q0 += XP * nt) {
+    uint4 v[XP];
 #pragma unroll
-    for (uint32_t j = 0; j < XB; ++j)
-      if (i0 + j * nt < e) v[j] = ld_coherent64(a.xch + i0 + j * nt);
+    for (uint32_t j = 0; j < XP; ++j)
+      if (q0 + j * nt < qe) v[j] = ld_coherent_pair(rs, q0 + j * nt);
     uint32_t pend = 0;
 #pragma unroll
-    for (uint32_t j = 0; j < XB; ++j) {
-      const uint32_t i = i0 + j * nt;
-      if (i < e) {
-        if (complete(v[j]))
-          lds[i] = (uint32_t)v[j];
-        else
-          pend |= 1u << j;
+    for (uint32_t j = 0; j < XP; ++j)
+      if (q0 + j * nt < qe) {
+        pend |= 3u << (2 * j);
+        put(q0 + j * nt, v[j], pend, j);
       }
-    }
     uint32_t polls = 0;
     while (pend != 0u) {
       if (give_up(a, polls)) {
@@ -426,14 +449,11 @@ __device__ __forceinline__ bool xch_phase_end(const AnnealArgs &a, uint32_t *lds
       }
       __builtin_amdgcn_s_sleep(2);
 #pragma unroll
-      for (uint32_t j = 0; j < XB; ++j)
-        if ((pend >> j) & 1u) v[j] = ld_coherent64(a.xch + i0 + j * nt);
+      for (uint32_t j = 0; j < XP; ++j)
+        if ((pend >> (2 * j)) & 3u) v[j] = ld_coherent_pair(rs, q0 + j * nt);
 #pragma unroll
-      for (uint32_t j = 0; j < XB; ++j)
-        if (((pend >> j) & 1u) && complete(v[j])) {
-          lds[i0 + j * nt] = (uint32_t)v[j];
-          pend &= ~(1u << j);
-        }
+      for (uint32_t j = 0; j < XP; ++j)
+        if ((pend >> (2 * j)) & 3u) put(q0 + j * nt, v[j], pend, j);
     }
   }
   if (!ok) s.ok = 0u;
@@ -948,9 +968,7 @@ __global__ __launch_bounds__(kAnnealBlock) void k_anneal(AnnealArgs a) {
           ita = ro_item(a.items, ib);
           fetch<L, ENC, FIELD, RC, USE_LDS>(a, ita, lane, fa, next_plane, lds);
         }
-        // (the larger register-resident variant has fewer registers to spare)
-        if (!done && !xch_phase_end<(RC > kResChunksSmall ? 4u : 8u)>(a, lds, ph, last_phase,
-                                                                      (uint32_t)(t - a.t_begin + 1), epoch, s_bar))
+        if (!done && !xch_phase_end<8u>(a, lds, ph, last_phase, (uint32_t)(t - a.t_begin + 1), epoch, s_bar))
           return;
       } else if (multi) {
         // without the LDS copy: a grid barrier ends every phase

@@ -9,12 +9,13 @@
 // block at counter {v, t div 4, r, 0}, key = seed, so one block serves four
 // consecutive sweeps.
 //
-// Work is issued in phases, each a run of colour classes.  In
-// deterministic mode a phase is one class, which makes the result equal to a
-// sequential sweep in (colour, id) order.  In async mode a phase merges
-// small classes, so neighbours inside a phase update concurrently and read
-// each other's value from this sweep or the previous one, as in the paper's
-// unsynchronised update, while every sweep stays synchronised.  Every
+// Work is issued in phases, each a run of classes.  In deterministic mode a
+// phase is one colour class, which makes the result equal to a sequential
+// sweep in (colour, id) order.  In async mode a phase is a run of classes
+// (or one near-independent part) with few edges inside, so neighbours inside
+// a phase update concurrently and read each other's value from this sweep or
+// the previous one, as in the paper's unsynchronised update, while every
+// sweep stays synchronised.  Every
 // wavefront keeps the loads of its next item in flight while it computes
 // the current one.
 //

@@ -375,6 +375,9 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     colorings = {"ff": I.COLOR_FIRST_FIT, "lf": I.COLOR_LARGEST_FIRST, "ni": I.COLOR_NEAR_INDEPENDENT}
+    if args.mode == "det" and args.coloring == "ni":
+        # deterministic sweeps need colour classes: the largest-first ones
+        args.coloring = "lf"
     gr = I.Graph(rp, cl, ww, n=g.n, replicas=R, coloring=colorings[args.coloring])
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0

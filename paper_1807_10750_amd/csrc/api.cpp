@@ -59,6 +59,9 @@ int64_t env_int(const char *name, int64_t dflt) {
 
 // Edges allowed inside one async phase, in units of 0.1 % of all edges.
 constexpr int64_t kAsyncMergeBudget = 10;
+// largest graph (directed entries) the near-independent part search runs on
+// (about 8 s on the host for 8M entries)
+constexpr int64_t kPartSearchMaxEntries = int64_t(1) << 25;
 
 int pow2_at_least(int x) {
   int p = 1;
@@ -576,9 +579,10 @@ ising_status_t create_impl(ising_graph_t *out, int64_t n, int64_t nnz, const int
   const double merge_budget = 0.001 * (double)std::max<int64_t>(0, env_int("ISING_ASYNC_MERGE", kAsyncMergeBudget));
   try {
     g->n_colors = greedy_coloring(csr, coloring != ISING_COLOR_FIRST_FIT, &g->color);
-    if (coloring == ISING_COLOR_NEAR_INDEPENDENT && n > 0) {
+    if (coloring == ISING_COLOR_NEAR_INDEPENDENT && n > 0 && nnz <= kPartSearchMaxEntries) {
       // fewer async phases than the largest-first colouring's runs, each
-      // within the same budget; otherwise the colouring stays
+      // within the same budget; otherwise the colouring stays (also above
+      // kPartSearchMaxEntries entries, where the search would take minutes)
       const int32_t runs = (int32_t)phase_runs(csr, g->color, g->n_colors, merge_budget).size() - 1;
       std::vector<int32_t> part;
       const int32_t K = near_independent_parts(csr, merge_budget, runs - 1, &part);

@@ -41,6 +41,8 @@ CASES = [
     ("reg3_pm1_20k", lambda: G.random_regular(20000, 3, "pm1", 1), 300),
     ("reg3_one_20k", lambda: G.random_regular(20000, 3, "one", 2), 300),
     ("torus200_pm1", lambda: G.torus(200, 200), 1000),
+    # a small dense graph: batched launch, one replica per workgroup
+    ("er800_one", lambda: G.erdos_renyi(800, 0.06, "one", 1), 1000),
 ]
 
 

@@ -38,7 +38,7 @@
 // sweep, so after sweep k of the call the count of word i is cover[i] * k
 // (an item that writes a word whole stores it outright with that count).
 // A phase ends with an arrival of every workgroup, a no-return add on one
-// of 32 counters, issued without waiting for its writes to land; once all
+// of 128 counters, issued without waiting for its writes to land; once all
 // have arrived a workgroup copies the phase's words into
 // LDS, and the counts show which words still have a write in flight (those
 // are read again).  No store-completion wait, no returned atomic and no
@@ -364,9 +364,9 @@ __device__ __forceinline__ void xch_store(const AnnealArgs &a, uint32_t w, uint3
 
 // Arrival at exchange epoch `epoch` (counted from 1 over the launch) and
 // the wait for every workgroup's arrival: once all its wavefronts are past
-// the phase, workgroup b adds one to counter b mod 32 (no return), and
+// the phase, workgroup b adds one to counter b mod 128 (no return), and
 // epoch e is complete when counter j reaches e times the number of
-// workgroups that use it; lane j of the first wavefront polls counter j.
+// workgroups that use it; thread j of the workgroup polls counter j.
 // Adds to one address serialise at the memory side (one counter for the
 // whole grid measured twice as slow as eight), hence many counters, each
 // on its own page.  ahead_gap: the sweep gap to record if another

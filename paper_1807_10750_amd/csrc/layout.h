@@ -62,8 +62,8 @@ constexpr int kBarCheck = 2;     // spin-value check result
 constexpr int kBarGap = 3;       // largest sweep gap between workgroups seen at a phase end
 constexpr int kBarGroup = 16;    // grid barrier: group counter k at kBarGroup + 16 * k, k < 8
 // phase-end arrival counters of the exchange words: counter j (workgroups
-// b mod 32 = j) at kBarArrive + j * kArriveStride, each in its own page
-constexpr int kArriveCounters = 32;
+// b mod 128 = j) at kBarArrive + j * kArriveStride, each in its own page
+constexpr int kArriveCounters = 128;
 constexpr int kArriveStride = 1088;  // words: 4 KiB + 256 B, so counters fall in different channels
 constexpr int kBarArrive = 1024;
 constexpr int kBarWords = kBarArrive + kArriveCounters * kArriveStride;

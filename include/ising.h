@@ -137,8 +137,10 @@ typedef enum { ISING_MODE_DETERMINISTIC = 0, ISING_MODE_ASYNC = 1 } ising_mode_t
  * fewest parts, each with at most 1 % of the edges inside it, that a
  * first-fit start plus a local search finds, when that is fewer than the
  * phases of the LARGEST_FIRST runs; each part is then one async phase.
- * Otherwise, and for graphs of more than 2^25 directed entries (where the
- * search would take minutes), the handle keeps the LARGEST_FIRST colouring.
+ * Otherwise, for graphs of more than 2^25 directed entries (where the
+ * search would take minutes) and for batches of graphs that take several
+ * bins (the budget holds per graph), the handle keeps the LARGEST_FIRST
+ * colouring.
  * With parts, DETERMINISTIC anneals return ISING_ERR_INVALID_ARGUMENT. */
 typedef enum {
   ISING_COLOR_FIRST_FIT = 0,

@@ -579,19 +579,6 @@ ising_status_t create_impl(ising_graph_t *out, int64_t n, int64_t nnz, const int
   const double merge_budget = 0.001 * (double)std::max<int64_t>(0, env_int("ISING_ASYNC_MERGE", kAsyncMergeBudget));
   try {
     g->n_colors = greedy_coloring(csr, coloring != ISING_COLOR_FIRST_FIT, &g->color);
-    if (coloring == ISING_COLOR_NEAR_INDEPENDENT && n > 0 && nnz <= kPartSearchMaxEntries) {
-      // fewer async phases than the largest-first colouring's runs, each
-      // within the same budget; otherwise the colouring stays (also above
-      // kPartSearchMaxEntries entries, where the search would take minutes)
-      const int32_t runs = (int32_t)phase_runs(csr, g->color, g->n_colors, merge_budget).size() - 1;
-      std::vector<int32_t> part;
-      const int32_t K = near_independent_parts(csr, merge_budget, runs - 1, &part);
-      if (K > 0) {
-        g->color.swap(part);
-        g->n_colors = K;
-        g->proper_classes = false;
-      }
-    }
   } catch (const std::bad_alloc &) {
     return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed while colouring"));
   }
@@ -624,6 +611,32 @@ ising_status_t create_impl(ising_graph_t *out, int64_t n, int64_t nnz, const int
   if (!g->batch) {
     bin_of.clear();
     n_bins = 1;
+  }
+  // Near-independent parts for one graph (a cooperative launch, or the one
+  // bin of a batched launch): fewer async phases than the largest-first
+  // colouring's runs, each within the same budget; otherwise the colouring
+  // stays.  Not for batches of several bins (the budget holds per graph),
+  // nor above kPartSearchMaxEntries entries, where the search would take
+  // minutes.
+  if (coloring == ISING_COLOR_NEAR_INDEPENDENT && n > 0 && nnz <= kPartSearchMaxEntries && n_bins == 1) {
+    try {
+      const int32_t runs = (int32_t)phase_runs(csr, g->color, g->n_colors, merge_budget).size() - 1;
+      std::vector<int32_t> part;
+      const int32_t K = near_independent_parts(csr, merge_budget, runs - 1, &part);
+      if (K > 0) {
+        g->color.swap(part);
+        g->n_colors = K;
+        g->proper_classes = false;
+        if (g->batch) {
+          std::vector<int64_t> cnt((size_t)K, 0);
+          for (int64_t v = 0; v < n; ++v) ++cnt[(size_t)g->color[v]];
+          max_bin_slots = 0;
+          for (int64_t c : cnt) max_bin_slots += (c + 63) / 64 * 64;
+        }
+      }
+    } catch (const std::bad_alloc &) {
+      return bail(fail(ISING_ERR_OUT_OF_MEMORY, "host allocation failed while searching parts"));
+    }
   }
   // replica packing: as many replicas per pass as fit an LDS copy of the state
   int64_t n_slots = 0;

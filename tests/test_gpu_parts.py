@@ -2,8 +2,9 @@
 
 The parts replace the colour classes as the async phases when they are
 fewer than the largest-first colouring's runs: each part keeps at most 1 %
-of the edges inside it, the same budget the runs keep (Sec. IV-B's update
-races only along such edges).  The mode is checked as async mode is: the mean
+of the edges inside it, the same budget the runs keep (only along such
+edges do two updates of one sweep race, the unsynchronised update of Sec.
+IV-B).  The mode is checked as async mode is: the mean
 final cut over seeds must agree with the oracle's sequential sweep within
 max(3 pooled standard errors, 0.5 % of the oracle mean), in both directions,
 and no two workgroups may be more than one sweep apart.  Deterministic
